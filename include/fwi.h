@@ -1,0 +1,163 @@
+/*
+ * fwi.h -- C-ABI of the MI355X (gfx950) k-space time-reversal gradient library.
+ *
+ * Method: Lucka, Perez-Liva, Treeby, Cox, "High Resolution 3D Ultrasonic
+ * Breast Imaging by Time-Domain Full Waveform Inversion" (arXiv 2102.00755).
+ *   - forward model  f = M A(u)^-1 s                      (Sec. 2.2, eq. USTmodel)
+ *   - misfit         D = 1/2 || f - f^delta ||^2           (Sec. 2.3, eq. FWI)
+ *   - gradient       dD/dc0 via adjoint + time reversal    (Sec. 2.3 eq. Gradc0,
+ *                                                           Sec. 3.1 eq. TRBwdWave,
+ *                                                           App. B, Algorithm 1)
+ *   - encoding       s_hat = sum_i w_i s_i, w_i = +-1      (Sec. 3.2, App. E)
+ *   - discretisation k-space pseudospectral scheme with split density and
+ *                    PML                                    (App. B, eq. DisPartDev,
+ *                                                           eq. DisPartDevSt)
+ *
+ * Conventions shared by every entry point
+ *   - Grids are [nz][ny][nx], x fastest, spacing dx in all three axes.  The
+ *     PML lies inside the grid (pml[a] cells at both ends of axis a).
+ *   - Every array argument of a compute entry point is a DEVICE pointer on the
+ *     handle's device, in the handle's precision ("real" = float when
+ *     precision == 4, double when precision == 8), allocated and owned by the
+ *     caller.  The library never frees or keeps caller pointers beyond a call.
+ *   - Batched entry points take B contiguous problems: [B][...] arrays.
+ *   - Calls are asynchronous on the given HIP stream (0 = null stream) unless
+ *     a flag requests a check that reads a device flag back.
+ *   - Return value: FWI_OK or one of the FWI_ERR_* codes; no exception or
+ *     abort crosses this boundary.  A handle is not thread-safe; distinct
+ *     handles may be used concurrently (on distinct streams).
+ *   - Supported sizes: nx even with nx/2 in, and ny, nz in, the set
+ *     {8, 12, 16, 24, 32, 40, 48, 56, 64, 80, 96, 112, 128, 160, 224, 256, 448};
+ *     other sizes return FWI_ERR_UNSUPPORTED.
+ */
+#ifndef FWI_H_
+#define FWI_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fwi_handle fwi_handle;
+typedef struct ihipStream_t* fwi_stream_t; /* a hipStream_t */
+
+enum {
+  FWI_OK = 0,
+  FWI_ERR_INVALID_ARG = 1,  /* bad shape/pointer/geometry, c outside [c_min,c_max] */
+  FWI_ERR_UNSUPPORTED = 2,  /* grid size not in the supported FFT set */
+  FWI_ERR_OOM = 3,          /* device allocation failed */
+  FWI_ERR_NO_TAPE = 4,      /* backward without a forward that saved the tape */
+  FWI_ERR_HIP = 5,          /* a HIP runtime call failed */
+  FWI_ERR_UNSTABLE = 6      /* non-finite value detected in the result */
+};
+
+/* Flags of fwi_forward / fwi_gradient / fwi_backward. */
+enum {
+  FWI_SAVE_TAPE = 1,    /* forward keeps the dGamma tape for fwi_backward     */
+  FWI_CHECK_INPUT = 2,  /* validate c in [c_min, c_max] (reads a flag back)   */
+  FWI_CHECK_FINITE = 4, /* check outputs are finite (reads a flag back)       */
+  FWI_TR_FINAL_STATE = 8 /* start the TR run from the final forward state
+                            instead of the paper's zero interior            */
+};
+
+/* Scheme parameters (App. B).  dt = cfl dx / c_max in the paper (Sec. 4.1). */
+typedef struct {
+  int32_t nx, ny, nz;   /* grid (FFT) sizes                                   */
+  double dx;            /* grid spacing [m]                                   */
+  double dt;            /* time step [s]                                      */
+  double c_ref;         /* k-space reference speed (paper: c_ref = c0^max)    */
+  double c_min, c_max;  /* admissible sound-speed bounds [m/s]                */
+  double rho0;          /* constant ambient density [kg/m^3]                  */
+  int32_t pml[3];       /* PML thickness in cells along x, y, z (inside grid) */
+  double pml_alpha;     /* PML strength: alpha = pml_alpha (c_ref/dx) (d/P)^4 */
+  int32_t nt;           /* number of time steps N                             */
+  int32_t precision;    /* 4 (float) or 8 (double)                            */
+  int32_t batch;        /* maximum number of problems per batched call (>=1) */
+} fwi_params;
+
+/* Geometry: transducer voxels and the region of interest (host arrays, read
+ * only during fwi_create).  Sources and receivers are point transducers
+ * snapped to voxels (Sec. 4.1); Gamma is the region where c0 is sought and
+ * dGamma the layer of Gamma voxels whose pressure is taped for the time
+ * reversal (Sec. 3.1, Sec. 4.2).  Duplicate source voxels, duplicate receiver
+ * voxels, transducers inside Gamma, dGamma voxels outside Gamma, and any of
+ * these inside the PML are rejected with FWI_ERR_INVALID_ARG. */
+typedef struct {
+  int32_t n_src;
+  const int32_t* src_ijk;        /* host [n_src][3] = (ix, iy, iz)           */
+  int32_t n_rec;
+  const int32_t* rec_ijk;        /* host [n_rec][3]                          */
+  const uint8_t* gamma_mask;     /* host [nz][ny][nx], nonzero inside Gamma  */
+  const uint8_t* boundary_mask;  /* host [nz][ny][nx], nonzero on dGamma     */
+} fwi_geometry;
+
+/* Create a handle on HIP device `device`: validates params and geometry,
+ * builds the operator tables (wavenumbers, kappa inputs, staggering phases,
+ * PML profiles: App. B) and allocates the whole workspace for `batch`
+ * problems (fields, spectra, tape).  *out is set to NULL on failure. */
+int fwi_create(const fwi_params* params, const fwi_geometry* geom, int device,
+               fwi_handle** out);
+
+/* Release the handle and all device memory it owns.  NULL is allowed. */
+void fwi_destroy(fwi_handle* h);
+
+/* Device bytes fwi_create would allocate for these params/geometry (the
+ * admission query of a serving loop).  Host-only; returns 0 on invalid input. */
+int64_t fwi_workspace_bytes(const fwi_params* params, const fwi_geometry* geom);
+
+/* Rademacher encoding weights (Sec. 3.2: w_i = +-1 with equal probability):
+ * w_out[i] = +1 if the top bit of the i-th output of SplitMix64 (Steele, Lea,
+ * Flood 2014) seeded with `seed` is 0, else -1.  Host array, n >= 0. */
+int fwi_rademacher(uint64_t seed, int32_t n, int8_t* w_out);
+
+/* Forward simulation (Alg. 1 forward iteration) of B problems:
+ *   c        [B][nz][ny][nx]  sound speed, in [c_min, c_max]
+ *   src_sig  [B][nt][n_src]   source signals s_i(t_n)
+ *   w        [B][n_src]       int8 weights in {-1, 0, +1}; encoded source
+ *                             s_hat = sum_i w_i s_i (Sec. 3.2, tau = 0)
+ *   traces   [B][nt][n_rec]   output f^n = M p^{n+1}, n = 0..nt-1
+ * With FWI_SAVE_TAPE the dGamma pressure history is kept in the handle for
+ * fwi_backward (B must then be <= batch). */
+int fwi_forward(fwi_handle* h, int32_t B, const void* c, const void* src_sig,
+                const int8_t* w, void* traces, int32_t flags, fwi_stream_t stream);
+
+/* Encoded TR gradient (Alg. 1) of B problems: forward with tape, residual
+ * r = f - f^delta, misfit D = 1/2 sum r^2 (FP64), then the interleaved
+ * adjoint and time-reversal simulations accumulating
+ *   G = sum_j 2/c0^3 p_adj^(j) (p_tr^(j) - 2 p_tr^(j+1) + p_tr^(j+2))  on Gamma.
+ *   obs      [B][nt][n_rec]   observed (encoded) data f^delta
+ *   misfit   [B] double       output D
+ *   grad     [B][nz][ny][nx]  output gradient, zero outside Gamma
+ * Three wave simulations per problem (Sec. 3.1). */
+int fwi_gradient(fwi_handle* h, int32_t B, const void* c, const void* src_sig,
+                 const int8_t* w, const void* obs, double* misfit, void* grad,
+                 int32_t flags, fwi_stream_t stream);
+
+/* Backward of the forward map c -> traces (the adjoint of Sec. 2.3 through
+ * time reversal): given residual = dL/df [B][nt][n_rec], returns
+ * grad = (df/dc)^T residual restricted to Gamma, recomputing the forward field
+ * by time reversal from the tape saved by the last fwi_forward with
+ * FWI_SAVE_TAPE (same B, same c).  misfit[b] = 1/2 ||residual_b||^2.
+ * Two wave simulations per problem.  FWI_ERR_NO_TAPE without a saved tape. */
+int fwi_backward(fwi_handle* h, int32_t B, const void* c, const void* residual,
+                 double* misfit, void* grad, int32_t flags, fwi_stream_t stream);
+
+/* One spectral derivative (eq. DisPartDevSt) of a field, for parity tests:
+ * out = Re F^-1 { i k_a kappa exp(sign i k_a dx/2) F{in} }, a in {0,1,2} =
+ * x, y, z, sign = +1 or -1.  in/out [nz][ny][nx] device, may not alias. */
+int fwi_derivative(fwi_handle* h, const void* in, void* out, int32_t axis, int32_t sign,
+                   fwi_stream_t stream);
+
+/* Human-readable text of a status code (static storage). */
+const char* fwi_status_string(int status);
+
+/* Last error detail recorded on this thread (static storage, may be ""). */
+const char* fwi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FWI_H_ */

@@ -1,0 +1,96 @@
+"""ctypes declarations of the C-ABI in include/fwi.h.
+
+Loads ``libfwi.so`` from this package directory.  There is no fallback: if
+the library is missing, importing the binding raises ``FwiLibraryMissing``.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int, c_int8, c_int32, c_int64, c_uint8, c_uint64, c_void_p
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfwi.so")
+
+FWI_OK = 0
+FWI_ERR_INVALID_ARG = 1
+FWI_ERR_UNSUPPORTED = 2
+FWI_ERR_OOM = 3
+FWI_ERR_NO_TAPE = 4
+FWI_ERR_HIP = 5
+FWI_ERR_UNSTABLE = 6
+
+FWI_SAVE_TAPE = 1
+FWI_CHECK_INPUT = 2
+FWI_CHECK_FINITE = 4
+FWI_TR_FINAL_STATE = 8
+
+SUPPORTED_LENGTHS = (8, 12, 16, 24, 32, 40, 48, 56, 64, 80, 96, 112, 128, 160, 224, 256, 448)
+
+# every symbol declared in include/fwi.h
+EXPORTED = (
+    "fwi_create", "fwi_destroy", "fwi_workspace_bytes", "fwi_rademacher", "fwi_forward",
+    "fwi_gradient", "fwi_backward", "fwi_derivative", "fwi_status_string", "fwi_last_error",
+)
+
+
+class FwiLibraryMissing(ImportError):
+    pass
+
+
+class FwiParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", c_int32), ("ny", c_int32), ("nz", c_int32),
+        ("dx", c_double), ("dt", c_double), ("c_ref", c_double),
+        ("c_min", c_double), ("c_max", c_double), ("rho0", c_double),
+        ("pml", c_int32 * 3), ("pml_alpha", c_double),
+        ("nt", c_int32), ("precision", c_int32), ("batch", c_int32),
+    ]
+
+
+class FwiGeometry(ctypes.Structure):
+    _fields_ = [
+        ("n_src", c_int32), ("src_ijk", POINTER(c_int32)),
+        ("n_rec", c_int32), ("rec_ijk", POINTER(c_int32)),
+        ("gamma_mask", POINTER(c_uint8)), ("boundary_mask", POINTER(c_uint8)),
+    ]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load and declare the library (once)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FwiLibraryMissing(
+            f"{path} not found: build it with `python -m paper_2102_00755_amd.build` "
+            "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    h = c_void_p
+    lib.fwi_create.argtypes = [POINTER(FwiParams), POINTER(FwiGeometry), c_int, POINTER(c_void_p)]
+    lib.fwi_create.restype = c_int
+    lib.fwi_destroy.argtypes = [h]
+    lib.fwi_destroy.restype = None
+    lib.fwi_workspace_bytes.argtypes = [POINTER(FwiParams), POINTER(FwiGeometry)]
+    lib.fwi_workspace_bytes.restype = c_int64
+    lib.fwi_rademacher.argtypes = [c_uint64, c_int32, POINTER(c_int8)]
+    lib.fwi_rademacher.restype = c_int
+    lib.fwi_forward.argtypes = [h, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]
+    lib.fwi_forward.restype = c_int
+    lib.fwi_gradient.argtypes = [h, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                 c_int32, c_void_p]
+    lib.fwi_gradient.restype = c_int
+    lib.fwi_backward.argtypes = [h, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]
+    lib.fwi_backward.restype = c_int
+    lib.fwi_derivative.argtypes = [h, c_void_p, c_void_p, c_int32, c_int32, c_void_p]
+    lib.fwi_derivative.restype = c_int
+    lib.fwi_status_string.argtypes = [c_int]
+    lib.fwi_status_string.restype = c_char_p
+    lib.fwi_last_error.argtypes = []
+    lib.fwi_last_error.restype = c_char_p
+    _lib = lib
+    return lib

@@ -1,0 +1,32 @@
+// Run-time dispatch from grid sizes to the compile-time FFT lengths.
+#pragma once
+
+#include "kernels.h"
+
+namespace fwi {
+
+// Supported FFT lengths (axis lengths ny, nz and half lengths nx/2).
+#define FWI_LENGTHS(X) \
+  X(8) X(12) X(16) X(24) X(32) X(40) X(48) X(56) X(64) X(80) X(96) X(112) X(128) X(160) X(224) X(256) X(448)
+
+inline bool length_supported(int L) {
+  switch (L) {
+#define FWI_CASE_TRUE(N) case N: return true;
+    FWI_LENGTHS(FWI_CASE_TRUE)
+#undef FWI_CASE_TRUE
+    default: return false;
+  }
+}
+
+// Each returns hipErrorInvalidValue for an unsupported length.
+template <typename T> hipError_t launch_axis_y(int L, bool inv, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
+template <typename T> hipError_t launch_axis_zm(int L, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
+template <typename T> hipError_t launch_axis_zp(int L, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
+template <typename T> hipError_t launch_x_vel(int M, dim3 grid, hipStream_t st, const XArgs<T>& a);
+template <typename T> hipError_t launch_x_den(int M, int mode, dim3 grid, hipStream_t st, const X2Args<T>& a);
+template <typename T> hipError_t launch_x_r2c(int M, dim3 grid, hipStream_t st, const XArgs<T>& a, const T* in, int f);
+template <typename T> hipError_t launch_x_c2r(int M, dim3 grid, hipStream_t st, const XArgs<T>& a, T* out, int f);
+
+template <typename T> inline int x_lines_per_block(int M) { return x_lpb<T>(M); }
+
+}  // namespace fwi

@@ -1,0 +1,248 @@
+// LDS-resident mixed-radix Stockham FFT for many short columns at once.
+//
+// A workgroup holds TW independent sequences ("columns") of length L in LDS,
+// element (row r, column c) at buf[r * TWP + c].  Consecutive lanes work on
+// consecutive columns of the same row, so every LDS access of a stage is a
+// run of consecutive 8/16-byte words (no bank conflicts when TWP*sizeof
+// is 128 B, or when TWP is odd).
+//
+// Each stage of radix R (Ns = product of the radices already applied) is the
+// Stockham autosort step of Govindaraju et al. (SC'08, "High performance
+// discrete Fourier transforms on graphics processors"): butterfly j reads
+// rows j + t L/R, multiplies input t by W_L^{t (j mod Ns) L/(Ns R)}, applies
+// an R-point DFT and writes rows (j/Ns) Ns R + (j mod Ns) + u Ns.  Every
+// thread first loads all its butterflies into registers, the workgroup
+// synchronises, then results are stored in place.  Twiddles come from a
+// table W_L^m computed in FP64 on the host and rounded once.
+//
+// Radices: 2, 3, 4, 5, 7, 8.  Odd radices use the symmetric form
+// y_k = x0 + sum_j (x_j + x_{R-j}) cos(2 pi j k / R) -+ i (x_j - x_{R-j}) sin(...).
+// Forward transforms use exp(-2 pi i / L); inverse ones are unnormalised.
+#pragma once
+
+#include "fwi_common.h"
+
+namespace fwi {
+
+struct RadixPlan {
+  int n;
+  int r[8];
+};
+
+constexpr RadixPlan make_plan(int L) {
+  RadixPlan p{0, {0, 0, 0, 0, 0, 0, 0, 0}};
+  int m = L;
+  while (m % 7 == 0) { p.r[p.n++] = 7; m /= 7; }
+  while (m % 5 == 0) { p.r[p.n++] = 5; m /= 5; }
+  while (m % 3 == 0) { p.r[p.n++] = 3; m /= 3; }
+  while (m > 1) {
+    if (m == 16) { p.r[p.n++] = 4; p.r[p.n++] = 4; m = 1; }
+    else if (m % 8 == 0) { p.r[p.n++] = 8; m /= 8; }
+    else if (m % 4 == 0) { p.r[p.n++] = 4; m /= 4; }
+    else { p.r[p.n++] = 2; m /= 2; }
+  }
+  return p;
+}
+
+constexpr bool plan_ok(int L) {
+  int m = L;
+  while (m % 7 == 0) m /= 7;
+  while (m % 5 == 0) m /= 5;
+  while (m % 3 == 0) m /= 3;
+  while (m % 2 == 0) m /= 2;
+  return m == 1 && L >= 2;
+}
+
+constexpr int plan_prefix(int L, int s) {
+  RadixPlan p = make_plan(L);
+  int ns = 1;
+  for (int i = 0; i < s; ++i) ns *= p.r[i];
+  return ns;
+}
+
+// cos / sin of 2 pi m / R for the odd radices (m taken mod R)
+template <int R> struct OddConst;
+template <> struct OddConst<3> {
+  static constexpr double c(int m) { return m == 0 ? 1.0 : -0.5; }
+  static constexpr double s(int m) {
+    return m == 0 ? 0.0 : (m == 1 ? 0.8660254037844386467637231708 : -0.8660254037844386467637231708);
+  }
+};
+template <> struct OddConst<5> {
+  static constexpr double c(int m) {
+    return m == 0 ? 1.0 : (m == 1 || m == 4) ? 0.3090169943749474241022934172 : -0.8090169943749474241022934172;
+  }
+  static constexpr double s(int m) {
+    return m == 0 ? 0.0 : m == 1 ? 0.9510565162951535721164393334 : m == 2 ? 0.5877852522924731291687059546
+         : m == 3 ? -0.5877852522924731291687059546 : -0.9510565162951535721164393334;
+  }
+};
+template <> struct OddConst<7> {
+  static constexpr double c(int m) {
+    return m == 0 ? 1.0 : (m == 1 || m == 6) ? 0.6234898018587335305250048840
+         : (m == 2 || m == 5) ? -0.2225209339563144042889025645 : -0.9009688679024191262361023195;
+  }
+  static constexpr double s(int m) {
+    return m == 0 ? 0.0 : m == 1 ? 0.7818314824680298087084445267 : m == 2 ? 0.9749279121818236070181316830
+         : m == 3 ? 0.4338837391175581204757683328 : m == 4 ? -0.4338837391175581204757683328
+         : m == 5 ? -0.9749279121818236070181316830 : -0.7818314824680298087084445267;
+  }
+};
+
+// R-point DFT in place: y_u = sum_t x_t exp(-+ 2 pi i t u / R)
+template <int R, bool INV, typename C> struct Bfly;
+
+template <bool INV, typename C> struct Bfly<2, INV, C> {
+  static __device__ __forceinline__ void run(C* v) {
+    C a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <bool INV, typename C> struct Bfly<4, INV, C> {
+  static __device__ __forceinline__ void run(C* v) {
+    C a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+    C c = cadd(v[1], v[3]), d = crot<INV>(csub(v[1], v[3]));
+    v[0] = cadd(a, c);
+    v[2] = csub(a, c);
+    v[1] = cadd(b, d);
+    v[3] = csub(b, d);
+  }
+};
+
+template <bool INV, typename C> struct Bfly<8, INV, C> {
+  static __device__ __forceinline__ void run(C* v) {
+    using T = decltype(C::x);
+    const T h = (T)0.7071067811865475244008443621;
+    C e[4] = {v[0], v[2], v[4], v[6]};
+    C o[4] = {v[1], v[3], v[5], v[7]};
+    Bfly<4, INV, C>::run(e);
+    Bfly<4, INV, C>::run(o);
+    // W8^u o_u, W8 = exp(-+ i pi / 4)
+    C t1 = INV ? cmake<C>(h * (o[1].x - o[1].y), h * (o[1].x + o[1].y))
+               : cmake<C>(h * (o[1].x + o[1].y), h * (o[1].y - o[1].x));
+    C t2 = crot<INV>(o[2]);
+    C t3 = INV ? cmake<C>(-h * (o[3].x + o[3].y), h * (o[3].x - o[3].y))
+               : cmake<C>(h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y));
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], t1);
+    v[5] = csub(e[1], t1);
+    v[2] = cadd(e[2], t2);
+    v[6] = csub(e[2], t2);
+    v[3] = cadd(e[3], t3);
+    v[7] = csub(e[3], t3);
+  }
+};
+
+template <int R, bool INV, typename C> struct BflyOdd {
+  static __device__ __forceinline__ void run(C* v) {
+    using T = decltype(C::x);
+    constexpr int H = (R - 1) / 2;
+    C sp[H + 1], sm[H + 1];
+#pragma unroll
+    for (int j = 1; j <= H; ++j) {
+      sp[j] = cadd(v[j], v[R - j]);
+      sm[j] = csub(v[j], v[R - j]);
+    }
+    C y0 = v[0];
+#pragma unroll
+    for (int j = 1; j <= H; ++j) y0 = cadd(y0, sp[j]);
+    C out[R];
+    out[0] = y0;
+#pragma unroll
+    for (int k = 1; k <= H; ++k) {
+      C a = v[0];
+      C b = cmake<C>((T)0, (T)0);
+#pragma unroll
+      for (int j = 1; j <= H; ++j) {
+        const T cc = (T)OddConst<R>::c((j * k) % R);
+        const T ss = (T)OddConst<R>::s((j * k) % R);
+        a.x += sp[j].x * cc;
+        a.y += sp[j].y * cc;
+        b.x += sm[j].x * ss;
+        b.y += sm[j].y * ss;
+      }
+      // forward: y_k = a - i b, y_{R-k} = a + i b ; inverse: swapped
+      C mib = cmake<C>(b.y, -b.x);  // -i b
+      if (INV) {
+        out[k] = csub(a, mib);
+        out[R - k] = cadd(a, mib);
+      } else {
+        out[k] = cadd(a, mib);
+        out[R - k] = csub(a, mib);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < R; ++u) v[u] = out[u];
+  }
+};
+template <bool INV, typename C> struct Bfly<3, INV, C> : BflyOdd<3, INV, C> {};
+template <bool INV, typename C> struct Bfly<5, INV, C> : BflyOdd<5, INV, C> {};
+template <bool INV, typename C> struct Bfly<7, INV, C> : BflyOdd<7, INV, C> {};
+
+// One Stockham stage and the recursion over the plan.
+template <typename T, int L, int TW, int TWP, int NT, bool INV, int S>
+struct Stage {
+  static __device__ __forceinline__ void run(cplx<T>* buf, const cplx<T>* __restrict__ tw) {
+    constexpr RadixPlan P = make_plan(L);
+    if constexpr (S < P.n) {
+      using C = cplx<T>;
+      constexpr int R = P.r[S];
+      constexpr int NS = plan_prefix(L, S);
+      constexpr int LR = L / R;
+      constexpr int NB = LR * TW;
+      constexpr int PER = (NB + NT - 1) / NT;
+      constexpr int TSTEP = L / (NS * R);
+      const int tid = threadIdx.x;
+      C v[PER][R];
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int q = i * NT + tid;
+        if (NB % NT == 0 || q < NB) {
+          const int c = q % TW;
+          const int j = q / TW;
+          const int jj = j % NS;
+#pragma unroll
+          for (int t = 0; t < R; ++t) {
+            C x = buf[(j + t * LR) * TWP + c];
+            if (NS > 1 && t > 0) {
+              C w = tw[t * jj * TSTEP];
+              if (INV) w = cconj(w);
+              x = cmul(x, w);
+            }
+            v[i][t] = x;
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int q = i * NT + tid;
+        if (NB % NT == 0 || q < NB) {
+          const int c = q % TW;
+          const int j = q / TW;
+          const int jj = j % NS;
+          const int k = j / NS;
+          Bfly<R, INV, C>::run(v[i]);
+#pragma unroll
+          for (int u = 0; u < R; ++u) buf[(k * NS * R + jj + u * NS) * TWP + c] = v[i][u];
+        }
+      }
+      __syncthreads();
+      Stage<T, L, TW, TWP, NT, INV, S + 1>::run(buf, tw);
+    }
+  }
+};
+
+// In-place length-L FFT of TW columns in LDS.  Must be called by all NT
+// threads of the workgroup; begins and ends with the LDS contents valid for
+// every thread (the caller synchronises before the call).
+template <typename T, int L, int TW, int TWP, int NT, bool INV>
+__device__ __forceinline__ void lds_fft(cplx<T>* buf, const cplx<T>* __restrict__ tw) {
+  static_assert(plan_ok(L), "FFT length must factor into 2, 3, 5, 7");
+  Stage<T, L, TW, TWP, NT, INV, 0>::run(buf, tw);
+}
+
+}  // namespace fwi

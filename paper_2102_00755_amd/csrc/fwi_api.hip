@@ -1,0 +1,757 @@
+// Host side of the C-ABI (include/fwi.h): handle, operator tables, geometry
+// tables, workspace and the time loops of Alg. 1.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/fwi.h"
+#include "dispatch.h"
+
+using namespace fwi;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define FWI_HIP(call)                                                                \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail(FWI_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));  \
+  } while (0)
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+// signed FFT frequency index (numpy fftfreq convention)
+inline int signed_freq(int i, int n) { return i < (n + 1) / 2 ? i : i - n; }
+
+// PML multiplier Lambda = exp(-alpha_pml (c_ref/dx) (d/P)^4 dt / 2) (App. B),
+// d = distance in cells into a PML of P cells; staggered points at i + 1/2.
+std::vector<double> pml_profile(int n, int P, double dx, double dt, double c_ref, double alpha, bool stag) {
+  std::vector<double> out(n, 1.0);
+  if (P == 0) return out;
+  for (int i = 0; i < n; ++i) {
+    const double s = i + (stag ? 0.5 : 0.0);
+    const double d = std::max(0.0, std::max(P - s, s - (n - 1 - P)));
+    const double a = alpha * (c_ref / dx) * std::pow(d / P, 4.0);
+    out[i] = std::exp(-a * dt / 2.0);
+  }
+  return out;
+}
+
+struct Geometry {
+  int nlines = 0;
+  std::vector<int32_t> src_off, rec_off, bnd_off, gam_off;
+  std::vector<int16_t> src_x, rec_x, bnd_x, gam_x;
+  std::vector<int32_t> src_id, rec_id, gam_lin;
+  int n_src = 0, n_rec = 0, n_bnd = 0, n_gam = 0;
+};
+
+bool in_pml(const fwi_params& p, int ix, int iy, int iz) {
+  return ix < p.pml[0] || ix > p.nx - 1 - p.pml[0] || iy < p.pml[1] || iy > p.ny - 1 - p.pml[1] ||
+         iz < p.pml[2] || iz > p.nz - 1 - p.pml[2];
+}
+
+int validate_params(const fwi_params* p) {
+  if (!p) return fail(FWI_ERR_INVALID_ARG, "params is NULL");
+  if (p->precision != 4 && p->precision != 8) return fail(FWI_ERR_INVALID_ARG, "precision must be 4 or 8");
+  if (p->nx <= 0 || p->ny <= 0 || p->nz <= 0 || (p->nx & 1)) return fail(FWI_ERR_INVALID_ARG, "bad grid size");
+  if (!length_supported(p->nx / 2) || !length_supported(p->ny) || !length_supported(p->nz))
+    return fail(FWI_ERR_UNSUPPORTED, "grid size not in the supported FFT set");
+  if (p->nx / 2 > 32767) return fail(FWI_ERR_UNSUPPORTED, "nx too large");
+  if (!(p->dx > 0) || !(p->dt > 0) || !(p->c_ref > 0) || !(p->rho0 > 0) || !(p->c_min > 0) ||
+      !(p->c_max >= p->c_min) || !(p->pml_alpha >= 0))
+    return fail(FWI_ERR_INVALID_ARG, "non-positive physical parameter");
+  if (p->nt < 1) return fail(FWI_ERR_INVALID_ARG, "nt must be >= 1");
+  if (p->batch < 1) return fail(FWI_ERR_INVALID_ARG, "batch must be >= 1");
+  for (int a = 0; a < 3; ++a) {
+    const int n = a == 0 ? p->nx : (a == 1 ? p->ny : p->nz);
+    if (p->pml[a] < 0 || 2 * p->pml[a] >= n) return fail(FWI_ERR_INVALID_ARG, "PML thicker than the grid");
+  }
+  // kappa's series is evaluated for c_ref dt |k| / 2 <= pi / 2
+  const double kmax2 = 3.0 * (kPi / p->dx) * (kPi / p->dx);
+  const double u = (p->c_ref * p->dt / 2) * (p->c_ref * p->dt / 2) * kmax2;
+  if (u > (kPi / 2) * (kPi / 2) * 1.0000001)
+    return fail(FWI_ERR_INVALID_ARG, "c_ref dt too large for the k-space operator (c_ref dt sqrt(3) pi / dx > pi)");
+  return FWI_OK;
+}
+
+int build_geometry(const fwi_params& p, const fwi_geometry* g, Geometry& out) {
+  if (!g) return fail(FWI_ERR_INVALID_ARG, "geometry is NULL");
+  if (g->n_src < 0 || g->n_rec < 0 || (g->n_src > 0 && !g->src_ijk) || (g->n_rec > 0 && !g->rec_ijk) ||
+      !g->gamma_mask || !g->boundary_mask)
+    return fail(FWI_ERR_INVALID_ARG, "geometry arrays missing");
+  const int nx = p.nx, ny = p.ny, nz = p.nz;
+  const int nlines = ny * nz;
+  out.nlines = nlines;
+  const uint8_t* gm = g->gamma_mask;
+  const uint8_t* bm = g->boundary_mask;
+  auto lin = [&](int ix, int iy, int iz) { return ((size_t)iz * ny + iy) * nx + ix; };
+  // transducers: per-line CSR, sorted by (line, x)
+  auto build_list = [&](int n, const int32_t* ijk, std::vector<int32_t>& off, std::vector<int16_t>& xs,
+                        std::vector<int32_t>& ids, const char* what) -> int {
+    std::vector<std::pair<long long, int>> key(n);
+    for (int i = 0; i < n; ++i) {
+      const int ix = ijk[3 * i], iy = ijk[3 * i + 1], iz = ijk[3 * i + 2];
+      if (ix < 0 || ix >= nx || iy < 0 || iy >= ny || iz < 0 || iz >= nz)
+        return fail(FWI_ERR_INVALID_ARG, std::string(what) + " outside the grid");
+      if (in_pml(p, ix, iy, iz)) return fail(FWI_ERR_INVALID_ARG, std::string(what) + " inside the PML");
+      if (gm[lin(ix, iy, iz)]) return fail(FWI_ERR_INVALID_ARG, std::string(what) + " inside Gamma");
+      key[i] = {(long long)lin(ix, iy, iz), i};
+    }
+    std::sort(key.begin(), key.end());
+    for (int i = 1; i < n; ++i)
+      if (key[i].first == key[i - 1].first) return fail(FWI_ERR_INVALID_ARG, std::string("duplicate ") + what + " voxel");
+    off.assign(nlines + 1, 0);
+    xs.resize(n);
+    ids.resize(n);
+    for (int i = 0; i < n; ++i) {
+      const long long L = key[i].first;
+      off[L / nx + 1]++;
+      xs[i] = (int16_t)(L % nx);
+      ids[i] = key[i].second;
+    }
+    for (int l = 0; l < nlines; ++l) off[l + 1] += off[l];
+    return FWI_OK;
+  };
+  int rc = build_list(g->n_src, g->src_ijk, out.src_off, out.src_x, out.src_id, "source");
+  if (rc) return rc;
+  rc = build_list(g->n_rec, g->rec_ijk, out.rec_off, out.rec_x, out.rec_id, "receiver");
+  if (rc) return rc;
+  out.n_src = g->n_src;
+  out.n_rec = g->n_rec;
+  // Gamma and dGamma in line-major order
+  out.gam_off.assign(nlines + 1, 0);
+  out.bnd_off.assign(nlines + 1, 0);
+  out.gam_x.clear();
+  out.bnd_x.clear();
+  out.gam_lin.clear();
+  for (int line = 0; line < nlines; ++line) {
+    const int iy = line % ny, iz = line / ny;
+    for (int ix = 0; ix < nx; ++ix) {
+      const size_t q = lin(ix, iy, iz);
+      if (bm[q] && !gm[q]) return fail(FWI_ERR_INVALID_ARG, "dGamma voxel outside Gamma");
+      if (gm[q]) {
+        if (in_pml(p, ix, iy, iz)) return fail(FWI_ERR_INVALID_ARG, "Gamma touches the PML");
+        out.gam_x.push_back((int16_t)ix);
+        out.gam_lin.push_back((int32_t)q);
+      }
+      if (bm[q]) out.bnd_x.push_back((int16_t)ix);
+    }
+    out.gam_off[line + 1] = (int32_t)out.gam_x.size();
+    out.bnd_off[line + 1] = (int32_t)out.bnd_x.size();
+  }
+  out.n_gam = (int)out.gam_x.size();
+  out.n_bnd = (int)out.bnd_x.size();
+  if ((long long)nx * ny * nz > 2147483647LL) return fail(FWI_ERR_UNSUPPORTED, "grid too large for int32 indices");
+  return FWI_OK;
+}
+
+inline int spec_pitch(const fwi_params& p) {
+  const int tw = p.precision == 4 ? 16 : 8;
+  const int mh = p.nx / 2 + 1;
+  return (mh + tw - 1) / tw * tw;
+}
+
+size_t align256(size_t n) { return (n + 255) / 256 * 256; }
+
+struct Layout {
+  size_t slots_bytes = 0;    // 2*batch slots
+  size_t slot_bytes = 0;
+  size_t tape_bytes = 0;
+  size_t traces_bytes = 0;   // internal traces
+  size_t adj_bytes = 0;
+  size_t ring_bytes = 0;
+  size_t gacc_bytes = 0;
+  size_t partial_bytes = 0;
+  size_t tables_bytes = 0;
+  size_t geom_bytes = 0;
+  size_t total = 0;
+};
+
+Layout make_layout(const fwi_params& p, const Geometry& g) {
+  Layout L;
+  const size_t rs = p.precision;
+  const size_t nfield = (size_t)p.nx * p.ny * p.nz;
+  const size_t nspec = (size_t)spec_pitch(p) * p.ny * p.nz;
+  L.slot_bytes = align256(6 * nfield * rs) + align256(3 * nspec * 2 * rs);
+  L.slots_bytes = 2 * (size_t)p.batch * L.slot_bytes;
+  L.tape_bytes = align256((size_t)p.batch * p.nt * std::max(g.n_bnd, 1) * rs);
+  L.traces_bytes = align256((size_t)p.batch * p.nt * std::max(g.n_rec, 1) * rs);
+  L.adj_bytes = L.traces_bytes;
+  L.ring_bytes = align256((size_t)p.batch * 3 * std::max(g.n_gam, 1) * rs);
+  L.gacc_bytes = align256((size_t)p.batch * std::max(g.n_gam, 1) * 8);
+  const int nblk = (std::max(g.n_rec, 1) + 255) / 256;
+  L.partial_bytes = align256((size_t)p.batch * nblk * 8);
+  const int M = p.nx / 2;
+  L.tables_bytes = align256(((size_t)M + p.ny + p.nz + (M + 1)) * 2 * rs) +
+                   align256(((size_t)(M + 1) + p.ny + p.nz) * rs) +
+                   align256(((size_t)(M + 1) + p.ny + p.nz) * 2 * 2 * rs) +
+                   align256(((size_t)p.nx + p.ny + p.nz) * 2 * rs) + 4096;
+  L.geom_bytes = align256(((size_t)g.nlines + 1) * 4 * 4) +
+                 align256(((size_t)g.n_src + g.n_rec + g.n_bnd + g.n_gam) * 2) +
+                 align256(((size_t)g.n_src + g.n_rec + g.n_gam) * 4) + 4096;
+  L.total = L.slots_bytes + L.tape_bytes + L.traces_bytes + L.adj_bytes + L.ring_bytes + L.gacc_bytes +
+            L.partial_bytes + L.tables_bytes + L.geom_bytes + 256;
+  return L;
+}
+
+// Device memory owned by a handle
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// typed engine
+// ---------------------------------------------------------------------------
+struct EngineBase {
+  virtual ~EngineBase() = default;
+  virtual int forward(int B, const void* c, const void* src, const int8_t* w, void* traces, int flags,
+                      hipStream_t st) = 0;
+  virtual int gradient(int B, const void* c, const void* src, const int8_t* w, const void* obs, double* misfit,
+                       void* grad, int flags, hipStream_t st) = 0;
+  virtual int backward(int B, const void* c, const void* resid, double* misfit, void* grad, int flags,
+                       hipStream_t st) = 0;
+  virtual int derivative(const void* in, void* out, int axis, int sign, hipStream_t st) = 0;
+};
+
+template <typename T> struct Engine : EngineBase {
+  using C = cplx<T>;
+  fwi_params p{};
+  Geometry geo;
+  Layout lay;
+  Dims d{};
+  int device = 0;
+  DevBuf mem_slots, mem_tape, mem_traces, mem_adj, mem_ring, mem_gacc, mem_partial, mem_tables, mem_geom,
+      mem_slot_table, mem_flag;
+  Tables<T> tb{};
+  LineGeom lg{};
+  Slot<T>* slot_table = nullptr;  // device [2*batch]
+  std::vector<Slot<T>> slots_host;
+  T* tape = nullptr;
+  T* traces_int = nullptr;
+  T* adj = nullptr;
+  T* ring = nullptr;
+  double* gacc = nullptr;
+  double* partial = nullptr;
+  int32_t* gam_lin = nullptr;
+  int* flag = nullptr;
+  int nblk_rec = 1;
+  bool tape_valid = false;
+  int tape_B = 0;
+  T scale = 0, kap_a = 0;
+
+  int init(const fwi_params& prm, Geometry&& g, int dev) {
+    p = prm;
+    geo = std::move(g);
+    device = dev;
+    lay = make_layout(p, geo);
+    FWI_HIP(hipSetDevice(device));
+    d.nx = p.nx; d.ny = p.ny; d.nz = p.nz; d.M = p.nx / 2; d.px = spec_pitch(p);
+    d.nfield = (long long)p.nx * p.ny * p.nz;
+    d.nspec = (long long)d.px * p.ny * p.nz;
+    d.nlines = p.ny * p.nz;
+    d.n_src = geo.n_src; d.n_rec = geo.n_rec; d.n_bnd = geo.n_bnd; d.n_gam = geo.n_gam;
+    d.nt = p.nt;
+    nblk_rec = (std::max(geo.n_rec, 1) + 255) / 256;
+    auto alloc = [&](DevBuf& b, size_t n) -> int {
+      if (hipMalloc(&b.p, std::max<size_t>(n, 256)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(FWI_ERR_OOM, "device allocation of " + std::to_string(n) + " bytes failed");
+      }
+      return FWI_OK;
+    };
+    int rc;
+    if ((rc = alloc(mem_slots, lay.slots_bytes))) return rc;
+    if ((rc = alloc(mem_tape, lay.tape_bytes))) return rc;
+    if ((rc = alloc(mem_traces, lay.traces_bytes))) return rc;
+    if ((rc = alloc(mem_adj, lay.adj_bytes))) return rc;
+    if ((rc = alloc(mem_ring, lay.ring_bytes))) return rc;
+    if ((rc = alloc(mem_gacc, lay.gacc_bytes))) return rc;
+    if ((rc = alloc(mem_partial, lay.partial_bytes))) return rc;
+    if ((rc = alloc(mem_tables, lay.tables_bytes))) return rc;
+    if ((rc = alloc(mem_geom, lay.geom_bytes))) return rc;
+    if ((rc = alloc(mem_slot_table, sizeof(Slot<T>) * 2 * p.batch))) return rc;
+    if ((rc = alloc(mem_flag, 256))) return rc;
+    tape = (T*)mem_tape.p;
+    traces_int = (T*)mem_traces.p;
+    adj = (T*)mem_adj.p;
+    ring = (T*)mem_ring.p;
+    gacc = (double*)mem_gacc.p;
+    partial = (double*)mem_partial.p;
+    flag = (int*)mem_flag.p;
+    // slots: [v0 v1 v2 rho0 rho1 rho2 | spec0 spec1 spec2], 2*batch of them
+    slots_host.resize(2 * p.batch);
+    char* base = (char*)mem_slots.p;
+    for (int s = 0; s < 2 * p.batch; ++s) {
+      char* sb = base + (size_t)s * lay.slot_bytes;
+      T* f = (T*)sb;
+      for (int a = 0; a < 3; ++a) {
+        slots_host[s].v[a] = f + (size_t)a * d.nfield;
+        slots_host[s].rho[a] = f + (size_t)(3 + a) * d.nfield;
+      }
+      C* sp = (C*)(sb + align256(6 * (size_t)d.nfield * sizeof(T)));
+      for (int a = 0; a < 3; ++a) slots_host[s].spec[a] = sp + (size_t)a * d.nspec;
+    }
+    slot_table = (Slot<T>*)mem_slot_table.p;
+    FWI_HIP(hipMemcpy(slot_table, slots_host.data(), sizeof(Slot<T>) * slots_host.size(), hipMemcpyHostToDevice));
+    if ((rc = build_tables())) return rc;
+    if ((rc = upload_geometry())) return rc;
+    // clear the whole workspace once so that no uninitialised value is ever read
+    FWI_HIP(hipMemset(mem_slots.p, 0, lay.slots_bytes));
+    FWI_HIP(hipMemset(mem_ring.p, 0, lay.ring_bytes));
+    FWI_HIP(hipDeviceSynchronize());
+    return FWI_OK;
+  }
+
+  int build_tables() {
+    const int M = d.M, nx = p.nx, ny = p.ny, nz = p.nz;
+    const double dx = p.dx;
+    std::vector<C> h_tw_x(M), h_tw_y(ny), h_tw_z(nz), h_rtw(M + 1);
+    auto W = [](long long m, long long n) {
+      const double ang = -2.0 * kPi * (double)m / (double)n;
+      C c;
+      c.x = (T)std::cos(ang);
+      c.y = (T)std::sin(ang);
+      return c;
+    };
+    for (int m = 0; m < M; ++m) h_tw_x[m] = W(m, M);
+    for (int m = 0; m < ny; ++m) h_tw_y[m] = W(m, ny);
+    for (int m = 0; m < nz; ++m) h_tw_z[m] = W(m, nz);
+    for (int k = 0; k <= M; ++k) h_rtw[k] = W(k, nx);
+    // wavenumbers: x half spectrum k = 0..M, y / z signed (fftfreq)
+    std::vector<double> kx(M + 1), ky(ny), kz(nz);
+    for (int i = 0; i <= M; ++i) kx[i] = 2.0 * kPi * i / (nx * dx);
+    for (int i = 0; i < ny; ++i) ky[i] = 2.0 * kPi * signed_freq(i, ny) / (ny * dx);
+    for (int i = 0; i < nz; ++i) kz[i] = 2.0 * kPi * signed_freq(i, nz) / (nz * dx);
+    const std::vector<double>* ks[3] = {&kx, &ky, &kz};
+    std::vector<T> h_ksq[3];
+    std::vector<C> h_sp[3], h_sm[3];
+    for (int a = 0; a < 3; ++a) {
+      const auto& k = *ks[a];
+      h_ksq[a].resize(k.size());
+      h_sp[a].resize(k.size());
+      h_sm[a].resize(k.size());
+      for (size_t i = 0; i < k.size(); ++i) {
+        h_ksq[a][i] = (T)(k[i] * k[i]);
+        // i k exp(+- i k dx / 2) = k (-sin(k dx/2), cos(k dx/2)) / k (sin, cos)
+        const double h = k[i] * dx / 2.0;
+        h_sp[a][i].x = (T)(-k[i] * std::sin(h));
+        h_sp[a][i].y = (T)(k[i] * std::cos(h));
+        h_sm[a][i].x = (T)(k[i] * std::sin(h));
+        h_sm[a][i].y = (T)(k[i] * std::cos(h));
+      }
+    }
+    const int lens[3] = {nx, ny, nz};
+    std::vector<T> h_pn[3], h_ps[3];
+    for (int a = 0; a < 3; ++a) {
+      auto pn = pml_profile(lens[a], p.pml[a], dx, p.dt, p.c_ref, p.pml_alpha, false);
+      auto ps = pml_profile(lens[a], p.pml[a], dx, p.dt, p.c_ref, p.pml_alpha, true);
+      h_pn[a].assign(pn.begin(), pn.end());
+      h_ps[a].assign(ps.begin(), ps.end());
+    }
+    scale = (T)(1.0 / ((double)nx * ny * nz));
+    kap_a = (T)((p.c_ref * p.dt / 2.0) * (p.c_ref * p.dt / 2.0));
+    // pack into the tables buffer
+    char* base = (char*)mem_tables.p;
+    size_t off = 0;
+    auto put = [&](const void* src, size_t bytes) -> void* {
+      void* dst = base + off;
+      off += align256(bytes);
+      return dst;
+    };
+    std::vector<std::pair<void*, std::pair<const void*, size_t>>> copies;
+    auto place = [&](const void* src, size_t bytes) -> void* {
+      void* dst = put(src, bytes);
+      copies.push_back({dst, {src, bytes}});
+      return dst;
+    };
+    tb.tw_x = (const C*)place(h_tw_x.data(), h_tw_x.size() * sizeof(C));
+    tb.tw_y = (const C*)place(h_tw_y.data(), h_tw_y.size() * sizeof(C));
+    tb.tw_z = (const C*)place(h_tw_z.data(), h_tw_z.size() * sizeof(C));
+    tb.rtw = (const C*)place(h_rtw.data(), h_rtw.size() * sizeof(C));
+    for (int a = 0; a < 3; ++a) {
+      tb.ksq[a] = (const T*)place(h_ksq[a].data(), h_ksq[a].size() * sizeof(T));
+      tb.sfac_p[a] = (const C*)place(h_sp[a].data(), h_sp[a].size() * sizeof(C));
+      tb.sfac_m[a] = (const C*)place(h_sm[a].data(), h_sm[a].size() * sizeof(C));
+      tb.pml_n[a] = (const T*)place(h_pn[a].data(), h_pn[a].size() * sizeof(T));
+      tb.pml_s[a] = (const T*)place(h_ps[a].data(), h_ps[a].size() * sizeof(T));
+    }
+    if (off > lay.tables_bytes) return fail(FWI_ERR_HIP, "internal: table layout overflow");
+    for (auto& c : copies) FWI_HIP(hipMemcpy(c.first, c.second.first, c.second.second, hipMemcpyHostToDevice));
+    return FWI_OK;
+  }
+
+  int upload_geometry() {
+    char* base = (char*)mem_geom.p;
+    size_t off = 0;
+    std::vector<std::pair<void*, std::pair<const void*, size_t>>> copies;
+    auto place = [&](const void* src, size_t bytes) -> void* {
+      void* dst = base + off;
+      off += align256(std::max<size_t>(bytes, 4));
+      if (bytes) copies.push_back({dst, {src, bytes}});
+      return dst;
+    };
+    lg.src_off = (const int32_t*)place(geo.src_off.data(), geo.src_off.size() * 4);
+    lg.rec_off = (const int32_t*)place(geo.rec_off.data(), geo.rec_off.size() * 4);
+    lg.bnd_off = (const int32_t*)place(geo.bnd_off.data(), geo.bnd_off.size() * 4);
+    lg.gam_off = (const int32_t*)place(geo.gam_off.data(), geo.gam_off.size() * 4);
+    lg.src_x = (const int16_t*)place(geo.src_x.data(), geo.src_x.size() * 2);
+    lg.rec_x = (const int16_t*)place(geo.rec_x.data(), geo.rec_x.size() * 2);
+    lg.bnd_x = (const int16_t*)place(geo.bnd_x.data(), geo.bnd_x.size() * 2);
+    lg.gam_x = (const int16_t*)place(geo.gam_x.data(), geo.gam_x.size() * 2);
+    lg.src_id = (const int32_t*)place(geo.src_id.data(), geo.src_id.size() * 4);
+    lg.rec_id = (const int32_t*)place(geo.rec_id.data(), geo.rec_id.size() * 4);
+    gam_lin = (int32_t*)place(geo.gam_lin.data(), geo.gam_lin.size() * 4);
+    if (off > lay.geom_bytes) return fail(FWI_ERR_HIP, "internal: geometry layout overflow");
+    for (auto& c : copies) FWI_HIP(hipMemcpy(c.first, c.second.first, c.second.second, hipMemcpyHostToDevice));
+    return FWI_OK;
+  }
+
+  // --- launch helpers -----------------------------------------------------
+  AxisArgs<T> axis_args(int slot0, int na, int slot1, int nf, int f0) const {
+    AxisArgs<T> a;
+    a.slots = slot_table; a.slot0 = slot0; a.na = na; a.slot1 = slot1; a.nf = nf; a.f0 = f0;
+    a.d = d; a.tb = tb; a.scale = scale; a.kap_a = kap_a;
+    return a;
+  }
+  int ntx() const { return (d.M + 1 + axis_tw<T>() - 1) / axis_tw<T>(); }
+
+  // the seven passes Y3 .. Y2 + X1 of one step on nslots slots
+  int step_spectral(int slot0, int na, int slot1, int nslots, hipStream_t st) {
+    const dim3 gy(ntx() * d.nz, nslots * 1), gy3(ntx() * d.nz, nslots * 3);
+    const dim3 gz(ntx() * d.ny, nslots), gz3(ntx() * d.ny, nslots * 3);
+    FWI_HIP(launch_axis_y<T>(d.ny, false, gy, st, axis_args(slot0, na, slot1, 1, 0)));       // Y3
+    FWI_HIP(launch_axis_zp<T>(d.nz, gz, st, axis_args(slot0, na, slot1, 1, 0)));             // Z2
+    FWI_HIP(launch_axis_y<T>(d.ny, true, gy3, st, axis_args(slot0, na, slot1, 3, 0)));       // Y4
+    XArgs<T> xa;
+    xa.slots = slot_table; xa.slot0 = slot0; xa.na = na; xa.slot1 = slot1;
+    xa.d = d; xa.tb = tb; xa.dt_rho = (T)(p.dt / p.rho0);
+    const int lpb = x_lines_per_block<T>(d.M);
+    FWI_HIP(launch_x_vel<T>(d.M, dim3((d.nlines + lpb - 1) / lpb, nslots), st, xa));       // X1
+    FWI_HIP(launch_axis_y<T>(d.ny, false, gy3, st, axis_args(slot0, na, slot1, 3, 0)));      // Y1
+    FWI_HIP(launch_axis_zm<T>(d.nz, gz3, st, axis_args(slot0, na, slot1, 3, 0)));            // Z1
+    FWI_HIP(launch_axis_y<T>(d.ny, true, gy3, st, axis_args(slot0, na, slot1, 3, 0)));       // Y2
+    return FWI_OK;
+  }
+
+  X2Args<T> x2_args(int B, const T* c) const {
+    X2Args<T> a{};
+    a.slots = slot_table; a.B = B; a.tr_off = p.batch;
+    a.d = d; a.tb = tb; a.g = lg;
+    a.dt_rho0 = (T)(p.dt * p.rho0);
+    a.src_k = (T)(2.0 * p.dt / (3.0 * p.dx));
+    a.c = c;
+    a.ring = ring; a.gacc = gacc;
+    return a;
+  }
+  int launch_x2(int mode, int B, const X2Args<T>& a, hipStream_t st) {
+    const int lpb = x_lines_per_block<T>(d.M);
+    FWI_HIP(launch_x_den<T>(d.M, mode, dim3((d.nlines + lpb - 1) / lpb, B), st, a));
+    return FWI_OK;
+  }
+
+  template <typename U> int fill(U* ptr, long long n, U v, hipStream_t st) {
+    if (n <= 0) return FWI_OK;
+    const int blocks = (int)std::min<long long>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL((k_fill<U>), dim3(blocks), dim3(256), 0, st, ptr, n, v);
+    FWI_HIP(hipGetLastError());
+    return FWI_OK;
+  }
+  // zero the whole state (v, rho, spectra) of slots [s0, s0 + n)
+  int zero_slots(int s0, int n, hipStream_t st) {
+    char* b = (char*)mem_slots.p + (size_t)s0 * lay.slot_bytes;
+    return fill<T>((T*)b, (long long)(n * lay.slot_bytes / sizeof(T)), (T)0, st);
+  }
+  int zero_velocity(int s, hipStream_t st) { return fill<T>(slots_host[s].v[0], 3 * d.nfield, (T)0, st); }
+
+  int check_c(int B, const T* c, hipStream_t st) {
+    FWI_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
+    const long long n = (long long)B * d.nfield;
+    const int blocks = (int)std::min<long long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL((k_check_range<T>), dim3(blocks), dim3(256), 0, st, c, n, (T)p.c_min, (T)p.c_max, flag);
+    FWI_HIP(hipGetLastError());
+    int h = 0;
+    FWI_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    FWI_HIP(hipStreamSynchronize(st));
+    if (h) return fail(FWI_ERR_INVALID_ARG, "sound speed outside [c_min, c_max] or not finite");
+    return FWI_OK;
+  }
+  int check_finite(const T* x, long long n, hipStream_t st) {
+    FWI_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
+    const int blocks = (int)std::min<long long>((n + 255) / 256, 4096);
+    const T big = (T)3.0e38;
+    hipLaunchKernelGGL((k_check_range<T>), dim3(blocks), dim3(256), 0, st, x, n, -big, big, flag);
+    FWI_HIP(hipGetLastError());
+    int h = 0;
+    FWI_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    FWI_HIP(hipStreamSynchronize(st));
+    if (h) return fail(FWI_ERR_UNSTABLE, "non-finite value in the result");
+    return FWI_OK;
+  }
+
+  // --- Alg. 1 forward iteration ------------------------------------------
+  int run_forward(int B, const T* c, const T* src, const int8_t* w, T* traces, bool save, hipStream_t st) {
+    const int tr0 = p.batch;
+    int rc;
+    if ((rc = zero_slots(tr0, B, st))) return rc;   // p^0 = 0, v = 0, rho = 0
+    X2Args<T> a = x2_args(B, c);
+    a.src_sig = src; a.w = w; a.traces = traces; a.tape = save ? tape : nullptr;
+    for (int n = 0; n < p.nt; ++n) {
+      if ((rc = step_spectral(tr0, B, tr0, B, st))) return rc;
+      a.step = n;
+      if ((rc = launch_x2(XM_FWD, B, a, st))) return rc;
+    }
+    return FWI_OK;
+  }
+
+  // --- Alg. 1 setup + interleaved adjoint / TR iterations ------------------
+  int run_adjoint_tr(int B, const T* c, const T* resid_or_obs, bool is_resid, const T* fwd_traces,
+                     double* misfit, T* grad, bool final_state, hipStream_t st) {
+    const int N = p.nt, tr0 = p.batch;
+    int rc;
+    // residual, misfit, reversed running sum (the adjoint source)
+    hipLaunchKernelGGL((k_residual<T>), dim3(nblk_rec, B), dim3(256), 0, st, fwd_traces, resid_or_obs,
+                       is_resid ? 1 : 0, adj, partial, N, d.n_rec);
+    FWI_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_misfit_final, dim3((B + 63) / 64), dim3(64), 0, st, partial, nblk_rec, misfit, B);
+    FWI_HIP(hipGetLastError());
+    if ((rc = fill<double>(gacc, (long long)B * d.n_gam, 0.0, st))) return rc;
+    if ((rc = zero_slots(0, B, st))) return rc;           // adjoint state
+    X2Args<T> a = x2_args(B, c);
+    a.adj_src = adj; a.tape = tape;
+    // TR initial state: zero interior (or the final forward state), dGamma <- g^{N-1}
+    if (final_state) {
+      // v <- -v^{N+1/2}: one more velocity half step of the forward, negated
+      return fail(FWI_ERR_INVALID_ARG, "FWI_TR_FINAL_STATE is not available in this build");
+    }
+    for (int b = 0; b < B; ++b)
+      if ((rc = zero_velocity(tr0 + b, st))) return rc;
+    a.tape_row = N - 1; a.tr_zero_state = 1; a.ring_c = 0; a.step = 0;
+    if ((rc = launch_x2(XM_TRONLY, B, a, st))) return rc;
+    a.tr_zero_state = 0;
+    if (N == 1) {  // p_tr^(1) = 0
+      if ((rc = fill<T>(ring, (long long)B * 3 * d.n_gam, (T)0, st))) return rc;
+    }
+    if (N >= 2) {  // advance the TR by one step to get ahead of the adjoint
+      if ((rc = step_spectral(tr0, B, tr0, B, st))) return rc;
+      a.tape_row = N - 2; a.ring_c = 1;
+      if ((rc = launch_x2(XM_TRONLY, B, a, st))) return rc;
+    }
+    for (int j = 0; j < N; ++j) {
+      const int k = j + 2;
+      a.step = j;
+      a.ring_a = j % 3; a.ring_b = (j + 1) % 3; a.ring_c = k % 3;
+      if (k <= N - 1) {
+        if ((rc = step_spectral(0, B, tr0, 2 * B, st))) return rc;
+        a.tape_row = N - 1 - k;
+        if ((rc = launch_x2(XM_PAIR, B, a, st))) return rc;
+      } else {
+        if ((rc = step_spectral(0, B, 0, B, st))) return rc;
+        if ((rc = launch_x2(XM_ADJONLY, B, a, st))) return rc;
+      }
+    }
+    // G on Gamma -> full grid, zero elsewhere
+    if ((rc = fill<T>(grad, (long long)B * d.nfield, (T)0, st))) return rc;
+    if (d.n_gam > 0) {
+      hipLaunchKernelGGL((k_grad_scatter<T>), dim3((d.n_gam + 255) / 256, B), dim3(256), 0, st, gacc, gam_lin,
+                         d.n_gam, d.nfield, grad, B);
+      FWI_HIP(hipGetLastError());
+    }
+    return FWI_OK;
+  }
+
+  int check_B(int B) {
+    if (B < 1 || B > p.batch) return fail(FWI_ERR_INVALID_ARG, "B outside [1, batch]");
+    return FWI_OK;
+  }
+
+  int forward(int B, const void* c, const void* src, const int8_t* w, void* traces, int flags,
+              hipStream_t st) override {
+    int rc;
+    if ((rc = check_B(B))) return rc;
+    if (!c || !traces || (d.n_src > 0 && (!src || !w))) return fail(FWI_ERR_INVALID_ARG, "NULL array argument");
+    FWI_HIP(hipSetDevice(device));
+    if (flags & FWI_CHECK_INPUT)
+      if ((rc = check_c(B, (const T*)c, st))) return rc;
+    const bool save = (flags & FWI_SAVE_TAPE) != 0;
+    tape_valid = false;
+    if ((rc = run_forward(B, (const T*)c, (const T*)src, w, (T*)traces, save, st))) return rc;
+    if (save) { tape_valid = true; tape_B = B; }
+    if (flags & FWI_CHECK_FINITE)
+      if ((rc = check_finite((const T*)traces, (long long)B * p.nt * d.n_rec, st))) return rc;
+    return FWI_OK;
+  }
+
+  int gradient(int B, const void* c, const void* src, const int8_t* w, const void* obs, double* misfit,
+               void* grad, int flags, hipStream_t st) override {
+    int rc;
+    if ((rc = check_B(B))) return rc;
+    if (!c || !obs || !misfit || !grad || (d.n_src > 0 && (!src || !w)))
+      return fail(FWI_ERR_INVALID_ARG, "NULL array argument");
+    FWI_HIP(hipSetDevice(device));
+    if (flags & FWI_CHECK_INPUT)
+      if ((rc = check_c(B, (const T*)c, st))) return rc;
+    tape_valid = false;
+    if ((rc = run_forward(B, (const T*)c, (const T*)src, w, traces_int, true, st))) return rc;
+    if ((rc = run_adjoint_tr(B, (const T*)c, (const T*)obs, false, traces_int, misfit, (T*)grad,
+                             (flags & FWI_TR_FINAL_STATE) != 0, st)))
+      return rc;
+    if (flags & FWI_CHECK_FINITE)
+      if ((rc = check_finite((const T*)grad, (long long)B * d.nfield, st))) return rc;
+    return FWI_OK;
+  }
+
+  int backward(int B, const void* c, const void* resid, double* misfit, void* grad, int flags,
+               hipStream_t st) override {
+    int rc;
+    if ((rc = check_B(B))) return rc;
+    if (!c || !resid || !misfit || !grad) return fail(FWI_ERR_INVALID_ARG, "NULL array argument");
+    if (!tape_valid || tape_B != B) return fail(FWI_ERR_NO_TAPE, "no saved tape for this batch size");
+    FWI_HIP(hipSetDevice(device));
+    if ((rc = run_adjoint_tr(B, (const T*)c, (const T*)resid, true, (const T*)resid, misfit, (T*)grad,
+                             (flags & FWI_TR_FINAL_STATE) != 0, st)))
+      return rc;
+    if (flags & FWI_CHECK_FINITE)
+      if ((rc = check_finite((const T*)grad, (long long)B * d.nfield, st))) return rc;
+    return FWI_OK;
+  }
+
+  int derivative(const void* in, void* out, int axis, int sign, hipStream_t st) override {
+    if (!in || !out || axis < 0 || axis > 2 || (sign != 1 && sign != -1))
+      return fail(FWI_ERR_INVALID_ARG, "bad derivative arguments");
+    FWI_HIP(hipSetDevice(device));
+    const int s = p.batch;   // scratch: the first forward slot
+    tape_valid = false;
+    XArgs<T> xa;
+    xa.slots = slot_table; xa.slot0 = s; xa.na = 1; xa.slot1 = s;
+    xa.d = d; xa.tb = tb; xa.dt_rho = (T)0;
+    const int lpb = x_lines_per_block<T>(d.M);
+    const dim3 gx((d.nlines + lpb - 1) / lpb, 1);
+    const int f = sign > 0 ? 0 : axis;
+    FWI_HIP(launch_x_r2c<T>(d.M, gx, st, xa, (const T*)in, f));
+    FWI_HIP(launch_axis_y<T>(d.ny, false, dim3(ntx() * d.nz, 1), st, axis_args(s, 1, s, 1, f)));
+    if (sign > 0) FWI_HIP(launch_axis_zp<T>(d.nz, dim3(ntx() * d.ny, 1), st, axis_args(s, 1, s, 1, 0)));
+    else FWI_HIP(launch_axis_zm<T>(d.nz, dim3(ntx() * d.ny, 1), st, axis_args(s, 1, s, 1, axis)));
+    FWI_HIP(launch_axis_y<T>(d.ny, true, dim3(ntx() * d.nz, 1), st, axis_args(s, 1, s, 1, axis)));
+    FWI_HIP(launch_x_c2r<T>(d.M, gx, st, xa, (T*)out, axis));
+    return FWI_OK;
+  }
+};
+
+struct fwi_handle {
+  std::unique_ptr<EngineBase> eng;
+  int precision = 4;
+};
+
+// ---------------------------------------------------------------------------
+// C-ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int fwi_create(const fwi_params* params, const fwi_geometry* geom, int device, fwi_handle** out) {
+  if (!out) return fail(FWI_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int rc = validate_params(params);
+  if (rc) return rc;
+  Geometry g;
+  if ((rc = build_geometry(*params, geom, g))) return rc;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    (void)hipGetLastError();
+    return fail(FWI_ERR_HIP, "no such HIP device");
+  }
+  std::unique_ptr<fwi_handle> h(new fwi_handle());
+  h->precision = params->precision;
+  if (params->precision == 4) {
+    auto e = std::make_unique<Engine<float>>();
+    if ((rc = e->init(*params, std::move(g), device))) return rc;
+    h->eng = std::move(e);
+  } else {
+    auto e = std::make_unique<Engine<double>>();
+    if ((rc = e->init(*params, std::move(g), device))) return rc;
+    h->eng = std::move(e);
+  }
+  *out = h.release();
+  return FWI_OK;
+}
+
+void fwi_destroy(fwi_handle* h) { delete h; }
+
+int64_t fwi_workspace_bytes(const fwi_params* params, const fwi_geometry* geom) {
+  if (validate_params(params)) return 0;
+  Geometry g;
+  if (build_geometry(*params, geom, g)) return 0;
+  Layout L = make_layout(*params, g);
+  return (int64_t)(L.total + sizeof(Slot<double>) * 2 * params->batch + 256);
+}
+
+int fwi_rademacher(uint64_t seed, int32_t n, int8_t* w_out) {
+  if (n < 0 || (n > 0 && !w_out)) return fail(FWI_ERR_INVALID_ARG, "bad arguments");
+  // SplitMix64 (Steele, Lea, Flood 2014): golden-ratio increment, Stafford
+  // variant-13 finaliser; output i uses state seed + (i + 1) * increment.
+  for (int32_t i = 0; i < n; ++i) {
+    uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z = z ^ (z >> 31);
+    w_out[i] = (z >> 63) ? (int8_t)-1 : (int8_t)1;
+  }
+  return FWI_OK;
+}
+
+int fwi_forward(fwi_handle* h, int32_t B, const void* c, const void* src_sig, const int8_t* w, void* traces,
+                int32_t flags, fwi_stream_t stream) {
+  if (!h) return fail(FWI_ERR_INVALID_ARG, "handle is NULL");
+  return h->eng->forward(B, c, src_sig, w, traces, flags, (hipStream_t)stream);
+}
+
+int fwi_gradient(fwi_handle* h, int32_t B, const void* c, const void* src_sig, const int8_t* w, const void* obs,
+                 double* misfit, void* grad, int32_t flags, fwi_stream_t stream) {
+  if (!h) return fail(FWI_ERR_INVALID_ARG, "handle is NULL");
+  return h->eng->gradient(B, c, src_sig, w, obs, misfit, grad, flags, (hipStream_t)stream);
+}
+
+int fwi_backward(fwi_handle* h, int32_t B, const void* c, const void* residual, double* misfit, void* grad,
+                 int32_t flags, fwi_stream_t stream) {
+  if (!h) return fail(FWI_ERR_INVALID_ARG, "handle is NULL");
+  return h->eng->backward(B, c, residual, misfit, grad, flags, (hipStream_t)stream);
+}
+
+int fwi_derivative(fwi_handle* h, const void* in, void* out, int32_t axis, int32_t sign, fwi_stream_t stream) {
+  if (!h) return fail(FWI_ERR_INVALID_ARG, "handle is NULL");
+  return h->eng->derivative(in, out, axis, sign, (hipStream_t)stream);
+}
+
+const char* fwi_status_string(int status) {
+  switch (status) {
+    case FWI_OK: return "ok";
+    case FWI_ERR_INVALID_ARG: return "invalid argument";
+    case FWI_ERR_UNSUPPORTED: return "unsupported size";
+    case FWI_ERR_OOM: return "out of device memory";
+    case FWI_ERR_NO_TAPE: return "no saved tape";
+    case FWI_ERR_HIP: return "HIP runtime error";
+    case FWI_ERR_UNSTABLE: return "non-finite result";
+    default: return "unknown status";
+  }
+}
+
+const char* fwi_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

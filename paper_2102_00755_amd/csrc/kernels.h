@@ -1,0 +1,714 @@
+// HIP kernels of one k-space time step (App. B) and of the TR gradient
+// (Alg. 1), written for gfx950.
+//
+// One time step of one simulation is eight launches, each one HBM pass:
+//   Y3  forward y-FFT of p_hat                       (1 field in place)
+//   Z2  forward z-FFT, x kappa * i k_a e^{+i k_a dx/2} for a = x,y,z,
+//       inverse z-FFT                                 (1 field -> 3 fields)
+//   Y4  inverse y-FFT                                 (3 fields in place)
+//   X1  inverse x (C2R) -> d+_a p, velocity update with PML, forward x (R2C)
+//   Y1  forward y-FFT                                 (3 fields)
+//   Z1  forward z-FFT, x kappa * i k_a e^{-i k_a dx/2}, inverse z-FFT
+//   Y2  inverse y-FFT                                 (3 fields)
+//   X2  inverse x (C2R) -> d-_a v_a, split-density update with PML, source /
+//       adjoint injection or Dirichlet imposition, equation of state, sensor
+//       sampling, boundary tape, gradient accumulation, forward x (R2C) of p
+// The k-space operator kappa = sinc(c_ref dt |k| / 2) is evaluated on the
+// fly (a Taylor series in u = (c_ref dt |k| / 2)^2) instead of being read
+// from HBM, and the 1/(nx ny nz) normalisation of the three unnormalised
+// inverse transforms is folded into the same multiplier.
+#pragma once
+
+#include "fft_engine.h"
+
+namespace fwi {
+
+// ----------------------------------------------------------------------------
+// launch geometry
+// ----------------------------------------------------------------------------
+template <typename T> constexpr int axis_tw() { return 128 / (int)(2 * sizeof(T)); }
+constexpr int axis_nt(int L, int TW) {
+  int n = L * TW / 8;
+  n = n < 64 ? 64 : (n > 256 ? 256 : n);
+  return (n + 63) / 64 * 64;
+}
+// x-lines per workgroup of the x passes
+template <typename T> constexpr int x_lpb(int M) {
+  int l = 1024 / M;
+  if (l > 16) l = 16;
+  int p = 1;
+  while (p * 2 <= l) p *= 2;
+  if (sizeof(T) == 8 && p > 1) p /= 2;
+  return p;
+}
+constexpr int X_NT = 256;
+
+// sinc(sqrt(u)) = sum_n (-1)^n u^n / (2n+1)!, n = 0..10 (accurate to double
+// rounding for sqrt(u) <= pi/2; the host rejects larger arguments)
+template <typename T> __device__ __forceinline__ T sinc_u(T u) {
+  T r = (T)(1.0 / 51090942171709440000.0);
+  r = r * u - (T)(1.0 / 121645100408832000.0);
+  r = r * u + (T)(1.0 / 355687428096000.0);
+  r = r * u - (T)(1.0 / 1307674368000.0);
+  r = r * u + (T)(1.0 / 6227020800.0);
+  r = r * u - (T)(1.0 / 39916800.0);
+  r = r * u + (T)(1.0 / 362880.0);
+  r = r * u - (T)(1.0 / 5040.0);
+  r = r * u + (T)(1.0 / 120.0);
+  r = r * u - (T)(1.0 / 6.0);
+  r = r * u + (T)1.0;
+  return r;
+}
+
+// ----------------------------------------------------------------------------
+// axis passes (y and z), tiles of L rows x TW consecutive kx columns
+// ----------------------------------------------------------------------------
+// Slots processed by one launch: i < na -> slot0 + i, else slot1 + (i - na)
+// (the adjoint slots and the forward / TR slots live in two ranges).
+template <typename T> struct AxisArgs {
+  const Slot<T>* slots;
+  int slot0;   // first slot of the first range
+  int na;      // slots in the first range
+  int slot1;   // first slot of the second range
+  int nf;      // fields per slot
+  int f0;      // first field
+  Dims d;
+  Tables<T> tb;
+  T scale;     // 1 / (nx ny nz)
+  T kap_a;     // (c_ref dt / 2)^2
+};
+
+__device__ __forceinline__ int slot_of(int i, int slot0, int na, int slot1) {
+  return i < na ? slot0 + i : slot1 + (i - na);
+}
+
+template <typename T, int L, int TW, int NT>
+__device__ __forceinline__ void tile_load(cplx<T>* buf, const cplx<T>* g, size_t rstride, int ncol) {
+  using C = cplx<T>;
+  constexpr int E = L * TW;
+#pragma unroll 4
+  for (int e = threadIdx.x; e < E; e += NT) {
+    const int r = e / TW, c = e % TW;
+    buf[e] = (c < ncol) ? g[(size_t)r * rstride + c] : cmake<C>((T)0, (T)0);
+  }
+}
+template <typename T, int L, int TW, int NT>
+__device__ __forceinline__ void tile_store(const cplx<T>* buf, cplx<T>* g, size_t rstride, int ncol) {
+  constexpr int E = L * TW;
+#pragma unroll 4
+  for (int e = threadIdx.x; e < E; e += NT) {
+    const int r = e / TW, c = e % TW;
+    if (c < ncol) g[(size_t)r * rstride + c] = buf[e];
+  }
+}
+
+// Y pass: in-place FFT along y of nf fields per slot.  L == ny.
+template <typename T, int L, bool INV>
+__global__ void __launch_bounds__(axis_nt(L, axis_tw<T>()))
+k_axis_y(AxisArgs<T> a) {
+  using C = cplx<T>;
+  constexpr int TW = axis_tw<T>();
+  constexpr int NT = axis_nt(L, TW);
+  __shared__ C buf[L * TW];
+  const int ntx = (a.d.M + TW) / TW;
+  const int tile = blockIdx.x % ntx;
+  const int z = blockIdx.x / ntx;
+  const int s = slot_of(blockIdx.y / a.nf, a.slot0, a.na, a.slot1);
+  const int f = a.f0 + blockIdx.y % a.nf;
+  const size_t px = a.d.px;
+  C* g = a.slots[s].spec[f] + (size_t)z * L * px + (size_t)tile * TW;
+  const int ncol = min(TW, a.d.M + 1 - tile * TW);
+  tile_load<T, L, TW, NT>(buf, g, px, ncol);
+  __syncthreads();
+  lds_fft<T, L, TW, TW, NT, INV>(buf, a.tb.tw_y);
+  tile_store<T, L, TW, NT>(buf, g, px, ncol);
+}
+
+// Z pass of the velocity divergence terms: field f -> F_z^-1 m-_f F_z field f
+// (eq. DisPartDevSt with the minus shift).  L == nz.
+template <typename T, int L>
+__global__ void __launch_bounds__(axis_nt(L, axis_tw<T>()))
+k_axis_z_minus(AxisArgs<T> a) {
+  using C = cplx<T>;
+  constexpr int TW = axis_tw<T>();
+  constexpr int NT = axis_nt(L, TW);
+  __shared__ C buf[L * TW];
+  const int ntx = (a.d.M + TW) / TW;
+  const int tile = blockIdx.x % ntx;
+  const int y = blockIdx.x / ntx;
+  const int s = slot_of(blockIdx.y / a.nf, a.slot0, a.na, a.slot1);
+  const int f = a.f0 + blockIdx.y % a.nf;
+  const size_t px = a.d.px;
+  const size_t rstride = (size_t)a.d.ny * px;
+  C* g = a.slots[s].spec[f] + (size_t)y * px + (size_t)tile * TW;
+  const int ncol = min(TW, a.d.M + 1 - tile * TW);
+  tile_load<T, L, TW, NT>(buf, g, rstride, ncol);
+  __syncthreads();
+  lds_fft<T, L, TW, TW, NT, false>(buf, a.tb.tw_z);
+  const T ky2 = a.tb.ksq[1][y];
+  const C sfy = a.tb.sfac_m[1][y];
+#pragma unroll 4
+  for (int e = threadIdx.x; e < L * TW; e += NT) {
+    const int r = e / TW, c = e % TW;
+    if (c < ncol) {
+      const int kx = tile * TW + c;
+      const T u = a.kap_a * (a.tb.ksq[0][kx] + ky2 + a.tb.ksq[2][r]);
+      const T kap = sinc_u(u) * a.scale;
+      const C sf = (f == 0) ? a.tb.sfac_m[0][kx] : ((f == 1) ? sfy : a.tb.sfac_m[2][r]);
+      buf[e] = cscale(cmul(sf, buf[e]), kap);
+    }
+  }
+  __syncthreads();
+  lds_fft<T, L, TW, TW, NT, true>(buf, a.tb.tw_z);
+  tile_store<T, L, TW, NT>(buf, g, rstride, ncol);
+}
+
+// Z pass of the pressure gradient: field 0 (p_hat) -> fields 0,1,2 =
+// F_z^-1 m+_a F_z p_hat for a = x, y, z.  L == nz.
+template <typename T, int L>
+__global__ void __launch_bounds__(axis_nt(L, axis_tw<T>()))
+k_axis_z_plus(AxisArgs<T> a) {
+  using C = cplx<T>;
+  constexpr int TW = axis_tw<T>();
+  constexpr int NT = axis_nt(L, TW);
+  constexpr int EPT = (L * TW + NT - 1) / NT;
+  __shared__ C buf[L * TW];
+  const int ntx = (a.d.M + TW) / TW;
+  const int tile = blockIdx.x % ntx;
+  const int y = blockIdx.x / ntx;
+  const int s = slot_of(blockIdx.y, a.slot0, a.na, a.slot1);
+  const size_t px = a.d.px;
+  const size_t rstride = (size_t)a.d.ny * px;
+  const size_t off = (size_t)y * px + (size_t)tile * TW;
+  const Slot<T> sl = a.slots[s];
+  const int ncol = min(TW, a.d.M + 1 - tile * TW);
+  tile_load<T, L, TW, NT>(buf, sl.spec[0] + off, rstride, ncol);
+  __syncthreads();
+  lds_fft<T, L, TW, TW, NT, false>(buf, a.tb.tw_z);
+  C xr[EPT];
+  T kr[EPT];
+  const T ky2 = a.tb.ksq[1][y];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * NT;
+    if (e < L * TW) {
+      const int r = e / TW, c = e % TW;
+      xr[i] = buf[e];
+      const int kx = min(tile * TW + c, a.d.M);
+      const T u = a.kap_a * (a.tb.ksq[0][kx] + ky2 + a.tb.ksq[2][r]);
+      kr[i] = sinc_u(u) * a.scale;
+    }
+  }
+  const C sfy = a.tb.sfac_p[1][y];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = threadIdx.x + i * NT;
+      if (e < L * TW) {
+        const int r = e / TW, c = e % TW;
+        const int kx = min(tile * TW + c, a.d.M);
+        const C sf = (f == 0) ? a.tb.sfac_p[0][kx] : ((f == 1) ? sfy : a.tb.sfac_p[2][r]);
+        buf[e] = cscale(cmul(sf, xr[i]), kr[i]);
+      }
+    }
+    __syncthreads();
+    lds_fft<T, L, TW, TW, NT, true>(buf, a.tb.tw_z);
+    tile_store<T, L, TW, NT>(buf, sl.spec[f] + off, rstride, ncol);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// x passes: LPB consecutive x-lines per workgroup, real <-> half spectrum
+// ----------------------------------------------------------------------------
+// Load NREG spectra lines (M+1 complex each) of LPB lines into columns
+// [col0, col0 + NREG*LPB) of buf (rows 0..M).
+template <typename T, int M, int LPB, int TWP>
+__device__ __forceinline__ void x_load_spectra(cplx<T>* buf, cplx<T>* const* spec, int nreg, int col0,
+                                               int l0, int nl, size_t px) {
+  using C = cplx<T>;
+  const int per = (M + 1) * LPB;
+  for (int e = threadIdx.x; e < nreg * per; e += X_NT) {
+    const int f = e / per;
+    const int rem = e % per;
+    const int l = rem / (M + 1), k = rem % (M + 1);
+    C v = cmake<C>((T)0, (T)0);
+    if (l < nl) v = spec[f][(size_t)(l0 + l) * px + k];
+    buf[k * TWP + col0 + f * LPB + l] = v;
+  }
+}
+template <typename T, int M, int LPB, int TWP>
+__device__ __forceinline__ void x_store_spectra(const cplx<T>* buf, cplx<T>* const* spec, int nreg, int col0,
+                                                int l0, int nl, size_t px) {
+  const int per = (M + 1) * LPB;
+  for (int e = threadIdx.x; e < nreg * per; e += X_NT) {
+    const int f = e / per;
+    const int rem = e % per;
+    const int l = rem / (M + 1), k = rem % (M + 1);
+    if (l < nl) spec[f][(size_t)(l0 + l) * px + k] = buf[k * TWP + col0 + f * LPB + l];
+  }
+}
+
+// Half spectrum X[0..M] of a length-2M real line -> Z[0..M-1] whose
+// unnormalised length-M inverse DFT is (y[2n] + i y[2n+1]) with y the
+// unnormalised length-2M inverse DFT of the Hermitian extension of X:
+//   Z[k] = (X[k] + conj X[M-k]) + i (X[k] - conj X[M-k]) W_2M^{-k}
+// Imaginary parts of X[0] and X[M] are dropped (real part of the inverse).
+template <typename T, int M, int TWP, int NCOL>
+__device__ __forceinline__ void c2r_pre(cplx<T>* buf, const cplx<T>* __restrict__ rtw) {
+  using C = cplx<T>;
+  for (int e = threadIdx.x; e < (M / 2 + 1) * NCOL; e += X_NT) {
+    const int col = e % NCOL, k = e / NCOL;
+    if (k == 0) {
+      const C x0 = buf[col], xm = buf[M * TWP + col];
+      buf[col] = cmake<C>(x0.x + xm.x, x0.x - xm.x);
+    } else {
+      const C A = buf[k * TWP + col], B = buf[(M - k) * TWP + col];
+      const C w = rtw[k];
+      const C s1 = cadd(A, cconj(B)), d1 = csub(A, cconj(B));
+      const C t1 = cmul(d1, cconj(w));                      // d1 W^{-k}
+      buf[k * TWP + col] = cmake<C>(s1.x - t1.y, s1.y + t1.x);  // s1 + i t1
+      if (k != M - k) {
+        const C s2 = cadd(B, cconj(A)), d2 = csub(B, cconj(A));
+        const C t2 = cmul(d2, cmake<C>(-w.x, -w.y));          // d2 W^{-(M-k)} = -d2 W^k
+        buf[(M - k) * TWP + col] = cmake<C>(s2.x - t2.y, s2.y + t2.x);
+      }
+    }
+  }
+}
+
+// Z[0..M-1] = DFT_M(x[2n] + i x[2n+1]) -> half spectrum X[0..M] of x:
+//   X[k] = (Z[k] + conj Z[M-k]) / 2 - i W_2M^k (Z[k] - conj Z[M-k]) / 2
+template <typename T, int M, int TWP, int NCOL>
+__device__ __forceinline__ void r2c_post(cplx<T>* buf, const cplx<T>* __restrict__ rtw) {
+  using C = cplx<T>;
+  const T h = (T)0.5;
+  for (int e = threadIdx.x; e < (M / 2 + 1) * NCOL; e += X_NT) {
+    const int col = e % NCOL, k = e / NCOL;
+    if (k == 0) {
+      const C z0 = buf[col];
+      buf[col] = cmake<C>(z0.x + z0.y, (T)0);
+      buf[M * TWP + col] = cmake<C>(z0.x - z0.y, (T)0);
+    } else {
+      const C A = buf[k * TWP + col], B = buf[(M - k) * TWP + col];
+      const C w = rtw[k];
+      const C s1 = cadd(A, cconj(B)), d1 = csub(A, cconj(B));
+      const C t1 = cmul(w, d1);                                  // W^k d1
+      buf[k * TWP + col] = cmake<C>(h * (s1.x + t1.y), h * (s1.y - t1.x));  // (s1 - i t1)/2
+      if (k != M - k) {
+        const C s2 = cadd(B, cconj(A)), d2 = csub(B, cconj(A));
+        const C t2 = cmul(cmake<C>(-w.x, w.y), d2);             // W^{M-k} = -conj(W^k)
+        buf[(M - k) * TWP + col] = cmake<C>(h * (s2.x + t2.y), h * (s2.y - t2.x));
+      }
+    }
+  }
+}
+
+template <typename T> struct XArgs {
+  const Slot<T>* slots;
+  int slot0, na, slot1;   // slot ranges as in AxisArgs
+  Dims d;
+  Tables<T> tb;
+  T dt_rho;   // dt / rho0
+};
+
+// X1: d+_a p (C2R of the three Z2/Y4 spectra), velocity update
+// v_a <- L^s_a (L^s_a v_a - dt/rho0 d+_a p) (Alg. 1 momentum step), R2C of v_a.
+template <typename T, int M>
+__global__ void __launch_bounds__(X_NT) k_x_velocity(XArgs<T> a) {
+  using C = cplx<T>;
+  constexpr int LPB = x_lpb<T>(M);
+  constexpr int NC = 3 * LPB;
+  constexpr int TWP = NC + 1;
+  __shared__ C buf[(M + 1) * TWP];
+  const int l0 = blockIdx.x * LPB;
+  const int nl = min(LPB, a.d.nlines - l0);
+  const Slot<T> sl = a.slots[slot_of(blockIdx.y, a.slot0, a.na, a.slot1)];
+  const size_t px = a.d.px;
+  x_load_spectra<T, M, LPB, TWP>(buf, sl.spec, 3, 0, l0, nl, px);
+  __syncthreads();
+  c2r_pre<T, M, TWP, NC>(buf, a.tb.rtw);
+  __syncthreads();
+  lds_fft<T, M, NC, TWP, X_NT, true>(buf, a.tb.tw_x);
+  const int nx = a.d.nx;
+  for (int e = threadIdx.x; e < M * LPB; e += X_NT) {
+    const int l = e / M, n = e % M;
+    if (l >= nl) continue;
+    const int line = l0 + l;
+    const int yy = line % a.d.ny, zz = line / a.d.ny;
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      const C dp = buf[n * TWP + f * LPB + l];
+      C* vp = reinterpret_cast<C*>(sl.v[f] + (size_t)line * nx) + n;
+      const C vv = *vp;
+      T lx, ly;
+      if (f == 0) { lx = a.tb.pml_s[0][2 * n]; ly = a.tb.pml_s[0][2 * n + 1]; }
+      else if (f == 1) { lx = ly = a.tb.pml_s[1][yy]; }
+      else { lx = ly = a.tb.pml_s[2][zz]; }
+      const C vn = cmake<C>(lx * (lx * vv.x - a.dt_rho * dp.x), ly * (ly * vv.y - a.dt_rho * dp.y));
+      *vp = vn;
+      buf[n * TWP + f * LPB + l] = vn;
+    }
+  }
+  __syncthreads();
+  lds_fft<T, M, NC, TWP, X_NT, false>(buf, a.tb.tw_x);
+  r2c_post<T, M, TWP, NC>(buf, a.tb.rtw);
+  __syncthreads();
+  x_store_spectra<T, M, LPB, TWP>(buf, sl.spec, 3, 0, l0, nl, px);
+}
+
+enum XMode { XM_FWD = 0, XM_PAIR = 1, XM_TRONLY = 2, XM_ADJONLY = 3 };
+
+template <typename T> struct X2Args {
+  const Slot<T>* slots;
+  int B;          // problems in this launch (grid.y)
+  int tr_off;     // slot index of problem b's forward/TR simulation = tr_off + b
+  Dims d;
+  Tables<T> tb;
+  LineGeom g;
+  T dt_rho0;      // dt * rho0
+  T src_k;        // 2 dt / (3 dx): mass-source conversion (divided by c0 at the voxel)
+  int step;       // forward iteration n, or adjoint iteration j
+  const T* c;            // [B][nfield]
+  const T* src_sig;      // [B][nt][n_src]
+  const int8_t* w;       // [B][n_src]
+  T* traces;             // [B][nt][n_rec]
+  T* tape;               // [B][nt][n_bnd] or null
+  const T* adj_src;      // [B][nt][n_rec]: a^j (reversed running sum of the residual)
+  int tape_row;          // TR: tape row imposed in this step
+  int tr_zero_state;     // TR: previous state is zero (initialisation)
+  T* ring;               // [B][3][n_gam]
+  int ring_a, ring_b, ring_c;
+  double* gacc;          // [B][n_gam]
+};
+
+enum SpKind { SP_SOURCE = 0, SP_ADJOINT = 1, SP_DIRICHLET = 2 };
+
+// Locate the local line of sparse entry i given the CSR offsets of lines
+// l0 .. l0+nl.
+__device__ __forceinline__ int local_line(const int32_t* off, int l0, int nl, int i) {
+  int l = 0;
+  while (l + 1 < nl && i >= off[l0 + l + 1]) ++l;
+  return l;
+}
+
+// Density update of one simulation slot for the workgroup's lines: C2R of
+// d-_a v_a, rho_a <- L_a (L_a rho_a - dt rho0 d-_a v_a) (+ injection, or
+// Dirichlet on dGamma), p = c0^2 sum_a rho_a written to column pcol of buf.
+template <typename T, int M, int LPB, int TWP, int KIND>
+__device__ __forceinline__ void density_update(const X2Args<T>& a, const Slot<T>& sl, int b, int l0, int nl,
+                                               bool zero_state, int pcol, cplx<T>* buf, cplx<T>* spv,
+                                               uint8_t* spm) {
+  using C = cplx<T>;
+  constexpr int NC = 3 * LPB;
+  const int nx = a.d.nx;
+  const size_t px = a.d.px;
+  const T* cb = a.c + (size_t)b * a.d.nfield;
+  if (!zero_state) x_load_spectra<T, M, LPB, TWP>(buf, sl.spec, 3, 0, l0, nl, px);
+  for (int e = threadIdx.x; e < M * LPB; e += X_NT) {
+    spv[e] = cmake<C>((T)0, (T)0);
+    if (KIND == SP_DIRICHLET) { spm[2 * e] = 0; spm[2 * e + 1] = 0; }
+  }
+  __syncthreads();
+  // sparse inputs of this step
+  if (KIND == SP_SOURCE) {
+    const int i0 = a.g.src_off[l0], i1 = a.g.src_off[l0 + nl];
+    for (int i = i0 + (int)threadIdx.x; i < i1; i += X_NT) {
+      const int l = local_line(a.g.src_off, l0, nl, i);
+      const int x = a.g.src_x[i], id = a.g.src_id[i];
+      const T cv = cb[(size_t)(l0 + l) * nx + x];
+      const T val = a.src_k / cv * (T)a.w[(size_t)b * a.d.n_src + id] *
+                    a.src_sig[((size_t)b * a.d.nt + a.step) * a.d.n_src + id];
+      T* sp = reinterpret_cast<T*>(spv);
+      sp[2 * ((x >> 1) * LPB + l) + (x & 1)] = val;
+    }
+  } else if (KIND == SP_ADJOINT) {
+    const int i0 = a.g.rec_off[l0], i1 = a.g.rec_off[l0 + nl];
+    for (int i = i0 + (int)threadIdx.x; i < i1; i += X_NT) {
+      const int l = local_line(a.g.rec_off, l0, nl, i);
+      const int x = a.g.rec_x[i], id = a.g.rec_id[i];
+      const T val = a.adj_src[((size_t)b * a.d.nt + a.step) * a.d.n_rec + id] * (T)(1.0 / 3.0);
+      T* sp = reinterpret_cast<T*>(spv);
+      sp[2 * ((x >> 1) * LPB + l) + (x & 1)] = val;
+    }
+  } else {
+    const int i0 = a.g.bnd_off[l0], i1 = a.g.bnd_off[l0 + nl];
+    const T* trow = a.tape + ((size_t)b * a.d.nt + a.tape_row) * a.d.n_bnd;
+    for (int i = i0 + (int)threadIdx.x; i < i1; i += X_NT) {
+      const int l = local_line(a.g.bnd_off, l0, nl, i);
+      const int x = a.g.bnd_x[i];
+      const T cv = cb[(size_t)(l0 + l) * nx + x];
+      const T val = trow[i] / ((T)3 * cv * cv);           // g / (3 c0^2)
+      T* sp = reinterpret_cast<T*>(spv);
+      const int q = 2 * ((x >> 1) * LPB + l) + (x & 1);
+      sp[q] = val;
+      spm[q] = 1;
+    }
+  }
+  if (!zero_state) {
+    c2r_pre<T, M, TWP, NC>(buf, a.tb.rtw);
+    __syncthreads();
+    lds_fft<T, M, NC, TWP, X_NT, true>(buf, a.tb.tw_x);
+  } else {
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < M * LPB; e += X_NT) {
+    const int l = e / M, n = e % M;
+    if (l >= nl) continue;
+    const int line = l0 + l;
+    const int yy = line % a.d.ny, zz = line / a.d.ny;
+    const C c2 = *(reinterpret_cast<const C*>(cb + (size_t)line * nx) + n);
+    const C sv = spv[n * LPB + l];
+    C sum = cmake<C>((T)0, (T)0);
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      C* rp = reinterpret_cast<C*>(sl.rho[f] + (size_t)line * nx) + n;
+      C rn;
+      if (zero_state) {
+        rn = cmake<C>((T)0, (T)0);
+      } else {
+        const C dv = buf[n * TWP + f * LPB + l];
+        const C rr = *rp;
+        T lx, ly;
+        if (f == 0) { lx = a.tb.pml_n[0][2 * n]; ly = a.tb.pml_n[0][2 * n + 1]; }
+        else if (f == 1) { lx = ly = a.tb.pml_n[1][yy]; }
+        else { lx = ly = a.tb.pml_n[2][zz]; }
+        rn = cmake<C>(lx * (lx * rr.x - a.dt_rho0 * dv.x), ly * (ly * rr.y - a.dt_rho0 * dv.y));
+      }
+      if (KIND == SP_DIRICHLET) {
+        if (spm[2 * (n * LPB + l)]) rn.x = sv.x;
+        if (spm[2 * (n * LPB + l) + 1]) rn.y = sv.y;
+      } else {
+        rn = cadd(rn, sv);
+      }
+      *rp = rn;
+      sum = cadd(sum, rn);
+    }
+    buf[n * TWP + pcol + l] = cmake<C>(c2.x * c2.x * sum.x, c2.y * c2.y * sum.y);
+  }
+  __syncthreads();
+}
+
+// read p at voxel x of local line l from the packed column pcol
+template <typename T, int TWP>
+__device__ __forceinline__ T p_at(const cplx<T>* buf, int pcol, int l, int x) {
+  const cplx<T> z = buf[(x >> 1) * TWP + pcol + l];
+  return (x & 1) ? z.y : z.x;
+}
+
+// X2: density / EOS pass.  MODE selects which simulations of problem b the
+// workgroup advances:
+//   XM_FWD     forward slot: sources, traces f^n, boundary tape g^n
+//   XM_PAIR    adjoint slot (receiver injection a^j/3) and TR slot (Dirichlet
+//              from the tape), gradient accumulation, TR ring update
+//   XM_TRONLY  TR slot only (initial state and the TR pre-step), ring update
+//   XM_ADJONLY adjoint slot and gradient with p_tr = 0 (last two iterations)
+template <typename T, int M, int MODE>
+__global__ void __launch_bounds__(X_NT) k_x_density(X2Args<T> a) {
+  using C = cplx<T>;
+  constexpr int LPB = x_lpb<T>(M);
+  constexpr int NP = (MODE == XM_PAIR) ? 2 : 1;
+  constexpr int NC = (3 + NP) * LPB;
+  constexpr int TWP = NC + 1;
+  __shared__ C buf[(M + 1) * TWP];
+  __shared__ C spv[M * LPB];
+  __shared__ uint8_t spm[(MODE == XM_PAIR || MODE == XM_TRONLY) ? 2 * M * LPB : 1];
+  const int l0 = blockIdx.x * LPB;
+  const int nl = min(LPB, a.d.nlines - l0);
+  const int b = blockIdx.y;
+  const int nx = a.d.nx;
+  const size_t px = a.d.px;
+  const int PA = 3 * LPB;               // column of the adjoint / forward pressure
+  const int PT = (NP == 2) ? 4 * LPB : 3 * LPB;  // column of the TR pressure
+  const Slot<T> s_adj = a.slots[b];
+  const Slot<T> s_tr = a.slots[a.tr_off + b];
+
+  if (MODE == XM_FWD) {
+    density_update<T, M, LPB, TWP, SP_SOURCE>(a, s_tr, b, l0, nl, false, PA, buf, spv, spm);
+    // sensors f^n = M p and boundary tape g^n = p(dGamma)
+    {
+      const int i0 = a.g.rec_off[l0], i1 = a.g.rec_off[l0 + nl];
+      for (int i = i0 + (int)threadIdx.x; i < i1; i += X_NT) {
+        const int l = local_line(a.g.rec_off, l0, nl, i);
+        a.traces[((size_t)b * a.d.nt + a.step) * a.d.n_rec + a.g.rec_id[i]] =
+            p_at<T, TWP>(buf, PA, l, a.g.rec_x[i]);
+      }
+      if (a.tape) {
+        const int j0 = a.g.bnd_off[l0], j1 = a.g.bnd_off[l0 + nl];
+        T* trow = a.tape + ((size_t)b * a.d.nt + a.step) * a.d.n_bnd;
+        for (int i = j0 + (int)threadIdx.x; i < j1; i += X_NT) {
+          const int l = local_line(a.g.bnd_off, l0, nl, i);
+          trow[i] = p_at<T, TWP>(buf, PA, l, a.g.bnd_x[i]);
+        }
+      }
+    }
+  }
+  if (MODE == XM_PAIR || MODE == XM_ADJONLY) {
+    density_update<T, M, LPB, TWP, SP_ADJOINT>(a, s_adj, b, l0, nl, false, PA, buf, spv, spm);
+  }
+  if (MODE == XM_PAIR || MODE == XM_TRONLY) {
+    density_update<T, M, LPB, TWP, SP_DIRICHLET>(a, s_tr, b, l0, nl, a.tr_zero_state != 0, PT, buf, spv, spm);
+  }
+  if (MODE != XM_FWD) {
+    // ring update and gradient: G += 2/c0^3 p_adj (p_tr^(j) - 2 p_tr^(j+1) + p_tr^(j+2))
+    const int i0 = a.g.gam_off[l0], i1 = a.g.gam_off[l0 + nl];
+    const T* cb = a.c + (size_t)b * a.d.nfield;
+    T* ring = a.ring + (size_t)b * 3 * a.d.n_gam;
+    double* gacc = a.gacc + (size_t)b * a.d.n_gam;
+    for (int i = i0 + (int)threadIdx.x; i < i1; i += X_NT) {
+      const int l = local_line(a.g.gam_off, l0, nl, i);
+      const int x = a.g.gam_x[i];
+      // p_tr^(k) = 0 for k >= N: the ring slot is written in every mode so
+      // that the next iteration never reads a stale entry
+      const T ptr = (MODE == XM_ADJONLY) ? (T)0 : p_at<T, TWP>(buf, PT, l, x);
+      if (MODE != XM_TRONLY) {
+        const T padj = p_at<T, TWP>(buf, PA, l, x);
+        const T cv = cb[(size_t)(l0 + l) * nx + x];
+        const T pm = ring[(size_t)a.ring_a * a.d.n_gam + i];
+        const T p0 = ring[(size_t)a.ring_b * a.d.n_gam + i];
+        const T inc = (T)2 / (cv * cv * cv) * padj * (pm - (T)2 * p0 + ptr);
+        gacc[i] += (double)inc;
+      }
+      ring[(size_t)a.ring_c * a.d.n_gam + i] = ptr;
+    }
+  }
+  __syncthreads();
+  // forward x-transform of the new pressure(s)
+  {
+    cplx<T>* pa_spec[1] = {(MODE == XM_TRONLY || MODE == XM_FWD) ? s_tr.spec[0] : s_adj.spec[0]};
+    const int c0 = (MODE == XM_TRONLY) ? PT : PA;
+    if (NP == 2) {
+      lds_fft<T, M, 2 * LPB, TWP, X_NT, false>(buf + PA, a.tb.tw_x);
+      r2c_post<T, M, TWP, 2 * LPB>(buf + PA, a.tb.rtw);
+      __syncthreads();
+      cplx<T>* specs[2] = {s_adj.spec[0], s_tr.spec[0]};
+      x_store_spectra<T, M, LPB, TWP>(buf, specs, 2, PA, l0, nl, px);
+    } else {
+      lds_fft<T, M, LPB, TWP, X_NT, false>(buf + c0, a.tb.tw_x);
+      r2c_post<T, M, TWP, LPB>(buf + c0, a.tb.rtw);
+      __syncthreads();
+      x_store_spectra<T, M, LPB, TWP>(buf, pa_spec, 1, c0, l0, nl, px);
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// small kernels
+// ----------------------------------------------------------------------------
+template <typename T>
+__global__ void k_fill(T* p, long long n, T v) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// Residual r^n = f^n - f^delta_n (or a given residual), adjoint source
+// a^j = sum_{i<=j} r^{N-1-i} and per-block FP64 partial sums of r^2.
+// grid: x over receivers (256 per block), y over problems.
+template <typename T>
+__global__ void __launch_bounds__(256) k_residual(const T* traces, const T* obs, int obs_is_residual, T* adj,
+                                                  double* partial, int nt, int n_rec) {
+  __shared__ double red[256];
+  const int b = blockIdx.y;
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  double s2 = 0.0;
+  if (r < n_rec) {
+    const size_t base = (size_t)b * nt * n_rec;
+    double acc = 0.0;
+    for (int j = 0; j < nt; ++j) {
+      const size_t src = base + (size_t)(nt - 1 - j) * n_rec + r;
+      const double rv = obs_is_residual ? (double)obs[src] : (double)traces[src] - (double)obs[src];
+      acc += rv;
+      s2 += rv * rv;
+      adj[base + (size_t)j * n_rec + r] = (T)acc;
+    }
+  }
+  red[threadIdx.x] = s2;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[(size_t)b * gridDim.x + blockIdx.x] = red[0];
+}
+
+static __global__ void k_misfit_final(const double* partial, int nblk, double* misfit, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B) {
+    double s = 0.0;
+    for (int i = 0; i < nblk; ++i) s += partial[(size_t)b * nblk + i];
+    misfit[b] = 0.5 * s;
+  }
+}
+
+template <typename T>
+__global__ void k_grad_scatter(const double* gacc, const int32_t* gam_lin, int n_gam, long long nfield, T* grad,
+                               int B) {
+  const int b = blockIdx.y;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_gam; i += gridDim.x * blockDim.x)
+    grad[(size_t)b * nfield + gam_lin[i]] = (T)gacc[(size_t)b * n_gam + i];
+}
+
+// flag |= 1 if any value lies outside [lo, hi] or is not finite
+template <typename T>
+__global__ void k_check_range(const T* p, long long n, T lo, T hi, int* flag) {
+  int bad = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const T v = p[i];
+    if (!(v >= lo && v <= hi)) bad = 1;
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+}  // namespace fwi
+
+namespace fwi {
+
+// Plain real-to-complex / complex-to-real x passes (used by the standalone
+// spectral derivative; the time step uses the fused X1 / X2 passes).
+template <typename T, int M>
+__global__ void __launch_bounds__(X_NT) k_x_r2c(XArgs<T> a, const T* in, int f) {
+  using C = cplx<T>;
+  constexpr int LPB = x_lpb<T>(M);
+  constexpr int TWP = LPB + 1;
+  __shared__ C buf[(M + 1) * TWP];
+  const int l0 = blockIdx.x * LPB;
+  const int nl = min(LPB, a.d.nlines - l0);
+  const Slot<T> sl = a.slots[a.slot0];
+  for (int e = threadIdx.x; e < M * LPB; e += X_NT) {
+    const int l = e / M, n = e % M;
+    buf[n * TWP + l] = (l < nl) ? reinterpret_cast<const C*>(in + (size_t)(l0 + l) * a.d.nx)[n]
+                                : cmake<C>((T)0, (T)0);
+  }
+  __syncthreads();
+  lds_fft<T, M, LPB, TWP, X_NT, false>(buf, a.tb.tw_x);
+  r2c_post<T, M, TWP, LPB>(buf, a.tb.rtw);
+  __syncthreads();
+  cplx<T>* specs[1] = {sl.spec[f]};
+  x_store_spectra<T, M, LPB, TWP>(buf, specs, 1, 0, l0, nl, a.d.px);
+}
+
+template <typename T, int M>
+__global__ void __launch_bounds__(X_NT) k_x_c2r(XArgs<T> a, T* out, int f) {
+  using C = cplx<T>;
+  constexpr int LPB = x_lpb<T>(M);
+  constexpr int TWP = LPB + 1;
+  __shared__ C buf[(M + 1) * TWP];
+  const int l0 = blockIdx.x * LPB;
+  const int nl = min(LPB, a.d.nlines - l0);
+  const Slot<T> sl = a.slots[a.slot0];
+  cplx<T>* specs[1] = {sl.spec[f]};
+  x_load_spectra<T, M, LPB, TWP>(buf, specs, 1, 0, l0, nl, a.d.px);
+  __syncthreads();
+  c2r_pre<T, M, TWP, LPB>(buf, a.tb.rtw);
+  __syncthreads();
+  lds_fft<T, M, LPB, TWP, X_NT, true>(buf, a.tb.tw_x);
+  for (int e = threadIdx.x; e < M * LPB; e += X_NT) {
+    const int l = e / M, n = e % M;
+    if (l < nl) reinterpret_cast<C*>(out + (size_t)(l0 + l) * a.d.nx)[n] = buf[n * TWP + l];
+  }
+}
+
+}  // namespace fwi

@@ -1,0 +1,187 @@
+"""Python binding of the C-ABI (argument marshalling only).
+
+Every step of the simulation and of the gradient runs in the HIP kernels of
+``libfwi.so``; PyTorch only provides device memory and the current stream.
+Functions take and return torch tensors on the handle's device.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+class FwiError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        lib = L.load()
+        msg = lib.fwi_status_string(status).decode()
+        detail = lib.fwi_last_error().decode()
+        super().__init__(f"{where}: {msg} ({detail})")
+        self.status = status
+
+
+def _check(status: int, where: str) -> None:
+    if status != L.FWI_OK:
+        raise FwiError(status, where)
+
+
+def rademacher(seed: int, n: int) -> np.ndarray:
+    """Rademacher weights from SplitMix64 (host, bit-exact); int8 [n]."""
+    lib = L.load()
+    out = np.empty(n, dtype=np.int8)
+    _check(lib.fwi_rademacher(ctypes.c_uint64(seed & ((1 << 64) - 1)), n,
+                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))), "fwi_rademacher")
+    return out
+
+
+def _params(shape, dx, dt, nt, c_ref, c_min, c_max, rho0, pml, pml_alpha, precision, batch):
+    nz, ny, nx = shape
+    p = L.FwiParams()
+    p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
+    p.dx, p.dt, p.c_ref = float(dx), float(dt), float(c_ref)
+    p.c_min, p.c_max, p.rho0 = float(c_min), float(c_max), float(rho0)
+    for a in range(3):
+        p.pml[a] = int(pml[a])
+    p.pml_alpha = float(pml_alpha)
+    p.nt, p.precision, p.batch = int(nt), int(precision), int(batch)
+    return p
+
+
+class _Geometry:
+    """Keeps the host arrays alive while the C struct points at them."""
+
+    def __init__(self, src_ijk, rec_ijk, gamma, boundary):
+        self.src = np.ascontiguousarray(np.asarray(src_ijk, dtype=np.int32).reshape(-1, 3))
+        self.rec = np.ascontiguousarray(np.asarray(rec_ijk, dtype=np.int32).reshape(-1, 3))
+        self.gamma = np.ascontiguousarray(np.asarray(gamma, dtype=np.uint8))
+        self.boundary = np.ascontiguousarray(np.asarray(boundary, dtype=np.uint8))
+        g = L.FwiGeometry()
+        g.n_src = self.src.shape[0]
+        g.src_ijk = self.src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        g.n_rec = self.rec.shape[0]
+        g.rec_ijk = self.rec.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        g.gamma_mask = self.gamma.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        g.boundary_mask = self.boundary.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        self.c = g
+
+
+def problem_kwargs(prob, precision: Optional[int] = None, nt: Optional[int] = None) -> dict:
+    """Handle arguments from a ``synth.Problem``-like object."""
+    return dict(shape=prob.shape, dx=prob.dx, dt=prob.dt, nt=nt or prob.nt, c_ref=prob.c_ref,
+                c_min=prob.c_min, c_max=prob.c_max, rho0=prob.rho0, pml=prob.pml,
+                pml_alpha=prob.pml_alpha, src_ijk=prob.src_ijk, rec_ijk=prob.rec_ijk,
+                gamma=prob.gamma, boundary=prob.boundary,
+                precision=precision or prob.precision)
+
+
+def workspace_bytes(**kw) -> int:
+    """Device bytes a handle with these arguments allocates (admission query)."""
+    lib = L.load()
+    batch = kw.pop("batch", 1)
+    geo = _Geometry(kw.pop("src_ijk"), kw.pop("rec_ijk"), kw.pop("gamma"), kw.pop("boundary"))
+    p = _params(kw["shape"], kw["dx"], kw["dt"], kw["nt"], kw["c_ref"], kw["c_min"], kw["c_max"],
+                kw["rho0"], kw["pml"], kw["pml_alpha"], kw.get("precision", 4), batch)
+    return int(lib.fwi_workspace_bytes(ctypes.byref(p), ctypes.byref(geo.c)))
+
+
+class Handle:
+    """One configured grid + geometry + workspace on one device."""
+
+    def __init__(self, *, shape, dx, dt, nt, c_ref, c_min, c_max, rho0, pml, pml_alpha,
+                 src_ijk, rec_ijk, gamma, boundary, precision=4, batch=1, device=0):
+        self._lib = L.load()
+        self._h = ctypes.c_void_p(None)
+        self.shape = tuple(int(s) for s in shape)
+        self.nt = int(nt)
+        self.precision = int(precision)
+        self.batch = int(batch)
+        self.device = torch.device("cuda", device)
+        self.dtype = torch.float32 if self.precision == 4 else torch.float64
+        geo = _Geometry(src_ijk, rec_ijk, gamma, boundary)
+        self.n_src = geo.src.shape[0]
+        self.n_rec = geo.rec.shape[0]
+        p = _params(shape, dx, dt, nt, c_ref, c_min, c_max, rho0, pml, pml_alpha, precision, batch)
+        with torch.cuda.device(self.device):
+            _check(self._lib.fwi_create(ctypes.byref(p), ctypes.byref(geo.c), int(device),
+                                        ctypes.byref(self._h)), "fwi_create")
+
+    @classmethod
+    def from_problem(cls, prob, batch=1, precision=None, nt=None, device=0):
+        return cls(**problem_kwargs(prob, precision, nt), batch=batch, device=device)
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            self._lib.fwi_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------
+    def _t(self, x, shape_tail, dtype=None):
+        dtype = dtype or self.dtype
+        t = torch.as_tensor(x, device=self.device, dtype=dtype)
+        if t.dim() == len(shape_tail):
+            t = t.unsqueeze(0)
+        if tuple(t.shape[1:]) != tuple(shape_tail):
+            raise ValueError(f"expected [..., {shape_tail}], got {tuple(t.shape)}")
+        return t.contiguous()
+
+    def _stream(self):
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def forward(self, c, src_sig, w, save_tape=False, check=False):
+        """Traces [B, nt, n_rec] of the encoded sources sum_i w_i s_i."""
+        c = self._t(c, self.shape)
+        B = c.shape[0]
+        src = self._t(src_sig, (self.nt, self.n_src))
+        w = self._t(w, (self.n_src,), torch.int8)
+        tr = torch.empty((B, self.nt, self.n_rec), device=self.device, dtype=self.dtype)
+        flags = (L.FWI_SAVE_TAPE if save_tape else 0) | (L.FWI_CHECK_INPUT if check else 0)
+        _check(self._lib.fwi_forward(self._h, B, c.data_ptr(), src.data_ptr(), w.data_ptr(),
+                                     tr.data_ptr(), flags, self._stream()), "fwi_forward")
+        return tr
+
+    def gradient(self, c, src_sig, w, obs, check=False, out=None) -> Tuple[torch.Tensor, torch.Tensor]:
+        """(misfit [B] float64, gradient [B, nz, ny, nx]) of the encoded TR gradient."""
+        c = self._t(c, self.shape)
+        B = c.shape[0]
+        src = self._t(src_sig, (self.nt, self.n_src))
+        w = self._t(w, (self.n_src,), torch.int8)
+        obs = self._t(obs, (self.nt, self.n_rec))
+        mis = torch.empty((B,), device=self.device, dtype=torch.float64)
+        grad = out if out is not None else torch.empty((B, *self.shape), device=self.device, dtype=self.dtype)
+        flags = L.FWI_CHECK_INPUT if check else 0
+        _check(self._lib.fwi_gradient(self._h, B, c.data_ptr(), src.data_ptr(), w.data_ptr(), obs.data_ptr(),
+                                      mis.data_ptr(), grad.data_ptr(), flags, self._stream()), "fwi_gradient")
+        return mis, grad
+
+    def backward(self, c, residual) -> Tuple[torch.Tensor, torch.Tensor]:
+        """(1/2 ||r||^2 [B], (df/dc)^T r on Gamma) using the tape of the last
+        forward(save_tape=True) call with the same batch."""
+        c = self._t(c, self.shape)
+        B = c.shape[0]
+        r = self._t(residual, (self.nt, self.n_rec))
+        mis = torch.empty((B,), device=self.device, dtype=torch.float64)
+        grad = torch.empty((B, *self.shape), device=self.device, dtype=self.dtype)
+        _check(self._lib.fwi_backward(self._h, B, c.data_ptr(), r.data_ptr(), mis.data_ptr(), grad.data_ptr(),
+                                      0, self._stream()), "fwi_backward")
+        return mis, grad
+
+    def derivative(self, field, axis: int, sign: int):
+        """Staggered spectral derivative (eq. DisPartDevSt) of one field."""
+        f = torch.as_tensor(field, device=self.device, dtype=self.dtype).contiguous()
+        if tuple(f.shape) != self.shape:
+            raise ValueError("field shape mismatch")
+        out = torch.empty_like(f)
+        _check(self._lib.fwi_derivative(self._h, f.data_ptr(), out.data_ptr(), int(axis), int(sign),
+                                        self._stream()), "fwi_derivative")
+        return out

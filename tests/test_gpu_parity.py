@@ -1,0 +1,136 @@
+"""GPU parity: the HIP path through the C-ABI against the FP64 oracle.
+
+Sizes span several tiles with a ragged tail (the half spectrum along x has
+nx/2 + 1 columns; axis tiles are 16 (FP32) / 8 (FP64) columns wide) and the
+radices 2, 3, 4, 5, 7, 8.  Tolerances: FP64 builds at round-off level; FP32
+rel l2 <= 1e-4 on traces and <= 1e-3 on gradients.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import kspace as ks
+from synth import make_small
+from synth.configs import random_traces
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def handle(prob, precision, batch=1):
+    from paper_2102_00755_amd.fwi import Handle
+    return Handle.from_problem(prob, batch=batch, precision=precision)
+
+
+SHAPES = [(16, 24, 32), (24, 40, 48), (24, 56, 112)]
+
+
+@pytest.mark.parametrize("precision,tol", [(8, 1e-12), (4, 2e-6)])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_derivative_matches_oracle(shape, precision, tol):
+    print(f"derivative shape={shape} precision={precision}", flush=True)
+    prob = make_small(shape=shape, nt=4, precision=precision)
+    h = handle(prob, precision)
+    sch = ks.scheme_for(prob)
+    rng = np.random.default_rng(3)
+    g = rng.standard_normal(shape)
+    for axis in range(3):
+        for sign in (+1, -1):
+            got = h.derivative(torch.from_numpy(g), axis, sign).cpu().numpy()
+            want = sch.d_plus(g, axis) if sign > 0 else sch.d_minus(g, axis)
+            assert rel(got, want) < tol, (axis, sign, rel(got, want))
+    h.close()
+
+
+def _inputs(prob, seed=0):
+    w = oracle.rademacher(prob.enc_seed, prob.n_src)
+    S = prob.src_signals()
+    return w, S
+
+
+@pytest.mark.parametrize("precision,tol", [(8, 1e-10), (4, 1e-4)])
+@pytest.mark.parametrize("shape", SHAPES[:2])
+def test_forward_matches_oracle(shape, precision, tol):
+    print(f"forward shape={shape} precision={precision}", flush=True)
+    prob = make_small(shape=shape, nt=60, n_src=3, n_rec=12, precision=precision)
+    w, S = _inputs(prob)
+    sch = ks.scheme_for(prob)
+    want = ks.forward(sch, prob.c_true, prob.src_ijk, S, w, prob.rec_ijk, prob.nt)["traces"]
+    h = handle(prob, precision)
+    got = h.forward(torch.from_numpy(prob.c_true), torch.from_numpy(S), torch.from_numpy(w))
+    got = got[0].cpu().numpy()
+    assert rel(got, want) < tol, rel(got, want)
+    h.close()
+
+
+@pytest.mark.parametrize("precision,ttol,gtol", [(8, 1e-10, 1e-9), (4, 1e-4, 1e-3)])
+@pytest.mark.parametrize("shape", SHAPES[:2])
+def test_tr_gradient_matches_oracle(shape, precision, ttol, gtol):
+    print(f"gradient shape={shape} precision={precision}", flush=True)
+    prob = make_small(shape=shape, nt=60, n_src=3, n_rec=12, layer=2, precision=precision)
+    w, S = _inputs(prob)
+    sch = ks.scheme_for(prob)
+    obs = ks.forward(sch, prob.c_true, prob.src_ijk, S, w, prob.rec_ijk, prob.nt)["traces"]
+    D, G, _ = ks.tr_gradient(sch, prob.c_eval, prob.src_ijk, S, w, prob.rec_ijk, obs, prob.gamma,
+                             prob.boundary, prob.nt)
+    h = handle(prob, precision)
+    mis, grad = h.gradient(torch.from_numpy(prob.c_eval), torch.from_numpy(S), torch.from_numpy(w),
+                           torch.from_numpy(obs))
+    assert abs(float(mis[0]) - D) <= ttol * D
+    gmask = prob.gamma.astype(bool)
+    got = grad[0].cpu().numpy()
+    assert np.all(got[~gmask] == 0)
+    assert rel(got[gmask], G[gmask]) < gtol, rel(got[gmask], G[gmask])
+    h.close()
+
+
+@pytest.mark.parametrize("precision,tol", [(8, 1e-9), (4, 1e-3)])
+def test_backward_matches_oracle(precision, tol):
+    shape = SHAPES[1]
+    prob = make_small(shape=shape, nt=50, n_src=2, n_rec=12, layer=2, precision=precision)
+    w, S = _inputs(prob)
+    sch = ks.scheme_for(prob)
+    r = random_traces(prob.nt, prob.n_rec, seed=11, scale=1e-3)
+    D, G, _ = ks.tr_gradient(sch, prob.c_eval, prob.src_ijk, S, w, prob.rec_ijk, None, prob.gamma,
+                             prob.boundary, prob.nt, residual=r)
+    h = handle(prob, precision)
+    c = torch.from_numpy(prob.c_eval)
+    h.forward(c, torch.from_numpy(S), torch.from_numpy(w), save_tape=True)
+    mis, grad = h.backward(c, torch.from_numpy(r))
+    gmask = prob.gamma.astype(bool)
+    assert abs(float(mis[0]) - D) <= 1e-6 * D
+    assert rel(grad[0].cpu().numpy()[gmask], G[gmask]) < tol
+    h.close()
+
+
+def test_batched_equals_individual():
+    shape = SHAPES[0]
+    probs = [make_small(shape=shape, nt=40, n_src=2, n_rec=12, layer=2, seed=s, precision=4)
+             for s in (21, 22, 23)]
+    base = probs[0]
+    h1 = handle(base, 4, batch=1)
+    h3 = handle(base, 4, batch=3)
+    S = base.src_signals()
+    cs, ws, obss = [], [], []
+    for i, p in enumerate(probs):
+        cs.append(p.c_eval)
+        ws.append(oracle.rademacher(100 + i, base.n_src))
+        obss.append(random_traces(base.nt, base.n_rec, seed=50 + i, scale=1e-3))
+    c = torch.from_numpy(np.stack(cs))
+    w = torch.from_numpy(np.stack(ws))
+    obs = torch.from_numpy(np.stack(obss))
+    Sb = torch.from_numpy(np.stack([S] * 3))
+    mb, gb = h3.gradient(c, Sb, w, obs)
+    for i in range(3):
+        m1, g1 = h1.gradient(c[i], Sb[i], w[i], obs[i])
+        assert torch.equal(g1[0].cpu(), gb[i].cpu())
+        assert float(m1[0]) == float(mb[i])
+    h1.close()
+    h3.close()
