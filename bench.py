@@ -1,0 +1,195 @@
+"""Benchmark: encoded TR gradient throughput on one MI355X.
+
+One step = one encoded time-reversal gradient (forward + adjoint + TR
+re-simulation, Alg. 1) of the full-size workload: 448x448x224 grid at
+0.5 mm, 20-cell PML, 2200 FP32 time steps, 32 Rademacher-encoded emitters,
+1024 receivers on a 2048-element golden-section bowl, breast-like phantom
+with 60 inclusions.  Inputs are synthetic and resident in HBM before timing.
+
+Prints one JSON line: throughput in Mcell-steps/s (3 simulations x cells x
+steps per gradient), p50/p99 solve latency, the HBM roofline of the dominant
+pass kernel (HIP events on the library's stream, sampled every few steps)
+and the FP64 oracle timed on the host on a truncated horizon.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Mcell-steps/s of TR-gradient at 448x448x224 FP32; p50/p99 solve latency"
+PEAK_HBM_GBS = 8000.0
+
+KERNEL_SYMBOLS = {
+    "y_fwd": "k_axis_y<float, {ny}, false>",
+    "y_inv": "k_axis_y<float, {ny}, true>",
+    "z_plus": "k_axis_z_plus<float, {nz}>",
+    "z_minus": "k_axis_z_minus<float, {nz}>",
+    "x_vel": "k_x_velocity<float, {m}>",
+    "x_den_fwd": "k_x_density<float, {m}, 0>",
+    "x_den_pair": "k_x_density<float, {m}, 1>",
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2, help="timed TR gradients")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed TR gradients")
+    ap.add_argument("--config", default="full", help="synth config name (default: the full-size workload)")
+    ap.add_argument("--nt", type=int, default=None, help="override the number of time steps")
+    ap.add_argument("--timing-every", type=int, default=16, help="sample pass launches every k steps")
+    ap.add_argument("--cpu-nt", type=int, default=2, help="time steps of the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(prob, nt_cpu: int) -> dict:
+    """FP64 oracle TR gradient of the same grid, geometry and medium on a
+    truncated horizon of nt_cpu steps, timed on this host."""
+    import numpy as np
+
+    from oracle import kspace as ks
+    from synth.configs import random_traces
+
+    w = ks.rademacher(prob.enc_seed, prob.n_src)
+    S = prob.src_signals()[:nt_cpu]
+    obs = random_traces(nt_cpu, prob.n_rec, seed=99, scale=1e-3)
+    t0 = time.perf_counter()
+    sch = ks.scheme_for(prob)
+    t1 = time.perf_counter()
+    ks.tr_gradient(sch, prob.c_eval, prob.src_ijk, S, w, prob.rec_ijk, obs, prob.gamma, prob.boundary, nt_cpu)
+    t2 = time.perf_counter()
+    work = 3.0 * prob.n_cells * nt_cpu
+    return {
+        "value": work / (t2 - t1) / 1e6,
+        "unit": "Mcell-steps/s",
+        "cores": int(ks._WORKERS),
+        "kind": "oracle",
+        "sample": (f"FP64 oracle TR gradient (forward + adjoint + TR) on the same "
+                   f"{prob.shape[2]}x{prob.shape[1]}x{prob.shape[0]} grid, geometry and medium, "
+                   f"truncated to {nt_cpu} time steps; operator setup ({t1 - t0:.1f} s) excluded; "
+                   f"scipy.fft workers={ks._WORKERS}; host {os.cpu_count()} logical CPUs"),
+        "seconds": round(t2 - t1, 3),
+    }
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU path "
+                          "(independent encoded gradients averaged across GPUs) is not built",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2102_00755_amd.fwi import Handle, rademacher
+    from synth import make_config
+
+    prob = make_config(args.config, nt=args.nt)
+    nz, ny, nx = prob.shape
+    h = Handle.from_problem(prob, batch=1, precision=4)
+    dev = h.device
+    w = torch.from_numpy(rademacher(prob.enc_seed, prob.n_src)).to(dev)
+    S = torch.from_numpy(prob.src_signals()).to(dev, torch.float32)
+    c_eval = torch.from_numpy(prob.c_eval).to(dev, torch.float32)
+    c_true = torch.from_numpy(prob.c_true).to(dev, torch.float32)
+    obs = h.forward(c_true, S, w)            # synthetic observed data (untimed)
+    torch.cuda.synchronize()
+    grad = torch.empty((1, nz, ny, nx), device=dev, dtype=torch.float32)
+    for _ in range(args.warmup):
+        h.gradient(c_eval, S, w, obs, out=grad)
+    torch.cuda.synchronize()
+
+    h.timing_enable(args.timing_every)
+    h.timing_read()
+    lat = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        mis, _ = h.gradient(c_eval, S, w, obs, out=grad)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    h.timing_enable(0)
+    passes = h.timing_read()
+    misfit = float(mis[0])
+    gfinite = bool(torch.isfinite(grad).all())
+
+    cells = prob.n_cells
+    work = 3.0 * cells * prob.nt * args.steps
+    value = work / total / 1e6
+    lat_ms = np.array(lat) * 1e3
+
+    per_pass = {}
+    for name, (n, ms, by) in passes.items():
+        if n:
+            per_pass[name] = {"launches_sampled": n, "avg_ms": ms / n, "GB/s": by / (ms * 1e-3) / 1e9,
+                              "bytes_per_launch": by / n}
+    dom = max(per_pass, key=lambda k: per_pass[k]["avg_ms"] * passes[k][0]) if per_pass else None
+    roof = None
+    if dom:
+        d = per_pass[dom]
+        roof = {
+            "bound": "hbm",
+            "achieved": round(d["GB/s"], 1),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(d["GB/s"] / PEAK_HBM_GBS, 4),
+            "traffic": None,
+            "kernel": KERNEL_SYMBOLS[dom].format(nx=nx, ny=ny, nz=nz, m=nx // 2),
+            "avg_ms": round(d["avg_ms"], 4),
+            "bytes_per_launch": d["bytes_per_launch"],
+        }
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "Mcell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(total / args.steps * 1e3, 2),
+        "p50_ms": round(float(np.percentile(lat_ms, 50)), 2),
+        "p99_ms": round(float(np.percentile(lat_ms, 99)), 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{args.config}: {nx}x{ny}x{nz} grid, dx {prob.dx * 1e3:g} mm, PML {prob.pml[0]}, "
+                         f"{prob.nt} FP32 time steps, {prob.n_src} Rademacher-encoded emitters, "
+                         f"{prob.n_rec} receivers, breast-like phantom; one encoded TR gradient "
+                         f"(3 wave simulations) per step"),
+            "grid": [nx, ny, nz], "nt": prob.nt, "n_src": prob.n_src, "n_rec": prob.n_rec,
+            "gamma_voxels": int(prob.gamma.sum()), "boundary_voxels": int(prob.boundary.sum()),
+        },
+        "roofline": roof,
+        "per_pass": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                     for k, v in per_pass.items()},
+        "misfit": misfit,
+        "grad_finite": gfinite,
+    }
+    h.close()
+    del obs, grad, c_eval, c_true, S
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_nt)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -150,6 +150,31 @@ int fwi_backward(fwi_handle* h, int32_t B, const void* c, const void* residual,
 int fwi_derivative(fwi_handle* h, const void* in, void* out, int32_t axis, int32_t sign,
                    fwi_stream_t stream);
 
+/* Pass kinds of one time step, for fwi_timing_* (one kernel symbol each). */
+enum {
+  FWI_PASS_Y_FWD = 0,    /* forward y-FFT                                     */
+  FWI_PASS_Y_INV = 1,    /* inverse y-FFT                                     */
+  FWI_PASS_Z_PLUS = 2,   /* z-FFT, k-space multiply for d+ (1 -> 3 fields)    */
+  FWI_PASS_Z_MINUS = 3,  /* z-FFT, k-space multiply for d- (3 -> 3 fields)    */
+  FWI_PASS_X_VEL = 4,    /* C2R, velocity update, R2C                         */
+  FWI_PASS_X_DEN_FWD = 5,  /* C2R, density/EOS/sources/sensors/tape, R2C       */
+  FWI_PASS_X_DEN_PAIR = 6, /* adjoint + TR density passes with gradient        */
+  FWI_PASS_COUNT = 7
+};
+
+/* Sampled timing of the pass launches, for roofline measurement: when
+ * every > 0, every `every`-th time step of subsequent forward / gradient /
+ * backward calls brackets each pass launch with two HIP events on the call's
+ * stream; the call then synchronises its stream once at its end to collect
+ * them.  every = 0 disables sampling. */
+int fwi_timing_enable(fwi_handle* h, int32_t every);
+
+/* Accumulated samples of one pass kind since the last read (then reset):
+ * number of sampled launches, their summed duration [ms] and the summed
+ * algorithmic HBM bytes of those launches (the bytes the pass must move:
+ * spectra, fields, sound speed, tape, ring and accumulator, counted once). */
+int fwi_timing_read(fwi_handle* h, int32_t pass, int64_t* launches, double* total_ms, double* total_bytes);
+
 /* Human-readable text of a status code (static storage). */
 const char* fwi_status_string(int status);
 

@@ -31,8 +31,13 @@ SUPPORTED_LENGTHS = (8, 12, 16, 24, 32, 40, 48, 56, 64, 80, 96, 112, 128, 160, 2
 # every symbol declared in include/fwi.h
 EXPORTED = (
     "fwi_create", "fwi_destroy", "fwi_workspace_bytes", "fwi_rademacher", "fwi_forward",
-    "fwi_gradient", "fwi_backward", "fwi_derivative", "fwi_status_string", "fwi_last_error",
+    "fwi_gradient", "fwi_backward", "fwi_derivative", "fwi_timing_enable", "fwi_timing_read",
+    "fwi_status_string", "fwi_last_error",
 )
+
+PASS_NAMES = ("y_fwd", "y_inv", "z_plus", "z_minus", "x_vel", "x_den_fwd", "x_den_pair")
+PASS_KERNELS = ("k_axis_y<*, false>", "k_axis_y<*, true>", "k_axis_z_plus", "k_axis_z_minus",
+                "k_x_velocity", "k_x_density<*, 0>", "k_x_density<*, 1>")
 
 
 class FwiLibraryMissing(ImportError):
@@ -88,6 +93,10 @@ def load(path: str = LIB_PATH):
     lib.fwi_backward.restype = c_int
     lib.fwi_derivative.argtypes = [h, c_void_p, c_void_p, c_int32, c_int32, c_void_p]
     lib.fwi_derivative.restype = c_int
+    lib.fwi_timing_enable.argtypes = [h, c_int32]
+    lib.fwi_timing_enable.restype = c_int
+    lib.fwi_timing_read.argtypes = [h, c_int32, POINTER(c_int64), POINTER(c_double), POINTER(c_double)]
+    lib.fwi_timing_read.restype = c_int
     lib.fwi_status_string.argtypes = [c_int]
     lib.fwi_status_string.restype = c_char_p
     lib.fwi_last_error.argtypes = []

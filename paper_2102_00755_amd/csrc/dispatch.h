@@ -28,5 +28,7 @@ template <typename T> hipError_t launch_x_r2c(int M, dim3 grid, hipStream_t st, 
 template <typename T> hipError_t launch_x_c2r(int M, dim3 grid, hipStream_t st, const XArgs<T>& a, T* out, int f);
 
 template <typename T> inline int x_lines_per_block(int M) { return x_lpb<T>(M); }
+template <typename T> inline int x_lines_per_block_vel(int M) { return x_lpb_vel<T>(M); }
+template <typename T> inline int x_lines_per_block_den(int M) { return x_lpb_den<T>(M); }
 
 }  // namespace fwi

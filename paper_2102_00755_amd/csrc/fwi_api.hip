@@ -159,7 +159,7 @@ int build_geometry(const fwi_params& p, const fwi_geometry* g, Geometry& out) {
 }
 
 inline int spec_pitch(const fwi_params& p) {
-  const int tw = p.precision == 4 ? 16 : 8;
+  const int tw = p.precision == 4 ? axis_tw<float>() : axis_tw<double>();
   const int mh = p.nx / 2 + 1;
   return (mh + tw - 1) / tw * tw;
 }
@@ -215,6 +215,72 @@ struct DevBuf {
   }
 };
 
+// Sampled HIP-event timing of pass launches (fwi_timing_enable / _read).
+struct PassTimer {
+  struct Pending {
+    hipEvent_t a, b;
+    int kind;
+    double bytes;
+  };
+  int every = 0;
+  bool active = false;   // sampling the current time step
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  int64_t launches[FWI_PASS_COUNT] = {};
+  double ms[FWI_PASS_COUNT] = {};
+  double bytes[FWI_PASS_COUNT] = {};
+
+  ~PassTimer() {
+    for (auto& p : pending) {
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void sample(int step) { active = every > 0 && (step % every) == 0; }
+  hipEvent_t begin(hipStream_t st) {
+    if (!active) return nullptr;
+    hipEvent_t a = get();
+    if (a) (void)hipEventRecord(a, st);
+    return a;
+  }
+  void end(hipEvent_t a, int kind, double nbytes, hipStream_t st) {
+    if (!a) return;
+    hipEvent_t b = get();
+    if (!b) { pool.push_back(a); return; }
+    (void)hipEventRecord(b, st);
+    pending.push_back({a, b, kind, nbytes});
+  }
+  hipError_t collect(hipStream_t st) {
+    active = false;
+    if (pending.empty()) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    for (auto& p : pending) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
+        launches[p.kind] += 1;
+        ms[p.kind] += t;
+        bytes[p.kind] += p.bytes;
+      }
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pending.clear();
+    return hipSuccess;
+  }
+};
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -229,6 +295,7 @@ struct EngineBase {
   virtual int backward(int B, const void* c, const void* resid, double* misfit, void* grad, int flags,
                        hipStream_t st) = 0;
   virtual int derivative(const void* in, void* out, int axis, int sign, hipStream_t st) = 0;
+  PassTimer timer;
 };
 
 template <typename T> struct Engine : EngineBase {
@@ -434,20 +501,40 @@ template <typename T> struct Engine : EngineBase {
   int ntx() const { return (d.M + 1 + axis_tw<T>() - 1) / axis_tw<T>(); }
 
   // the seven passes Y3 .. Y2 + X1 of one step on nslots slots
+  // algorithmic bytes of one half spectrum / one real field
+  double sbytes() const { return (double)(d.M + 1) * d.ny * d.nz * sizeof(C); }
+  double fbytes() const { return (double)d.nfield * sizeof(T); }
+
   int step_spectral(int slot0, int na, int slot1, int nslots, hipStream_t st) {
     const dim3 gy(ntx() * d.nz, nslots * 1), gy3(ntx() * d.nz, nslots * 3);
     const dim3 gz(ntx() * d.ny, nslots), gz3(ntx() * d.ny, nslots * 3);
+    const double S = sbytes(), F = fbytes(), ns = nslots;
+    hipEvent_t ev;
+    ev = timer.begin(st);
     FWI_HIP(launch_axis_y<T>(d.ny, false, gy, st, axis_args(slot0, na, slot1, 1, 0)));       // Y3
+    timer.end(ev, FWI_PASS_Y_FWD, 2 * ns * S, st);
+    ev = timer.begin(st);
     FWI_HIP(launch_axis_zp<T>(d.nz, gz, st, axis_args(slot0, na, slot1, 1, 0)));             // Z2
+    timer.end(ev, FWI_PASS_Z_PLUS, 4 * ns * S, st);
+    ev = timer.begin(st);
     FWI_HIP(launch_axis_y<T>(d.ny, true, gy3, st, axis_args(slot0, na, slot1, 3, 0)));       // Y4
+    timer.end(ev, FWI_PASS_Y_INV, 6 * ns * S, st);
     XArgs<T> xa;
     xa.slots = slot_table; xa.slot0 = slot0; xa.na = na; xa.slot1 = slot1;
     xa.d = d; xa.tb = tb; xa.dt_rho = (T)(p.dt / p.rho0);
-    const int lpb = x_lines_per_block<T>(d.M);
+    const int lpb = x_lines_per_block_vel<T>(d.M);
+    ev = timer.begin(st);
     FWI_HIP(launch_x_vel<T>(d.M, dim3((d.nlines + lpb - 1) / lpb, nslots), st, xa));       // X1
+    timer.end(ev, FWI_PASS_X_VEL, ns * (6 * S + 6 * F), st);
+    ev = timer.begin(st);
     FWI_HIP(launch_axis_y<T>(d.ny, false, gy3, st, axis_args(slot0, na, slot1, 3, 0)));      // Y1
+    timer.end(ev, FWI_PASS_Y_FWD, 6 * ns * S, st);
+    ev = timer.begin(st);
     FWI_HIP(launch_axis_zm<T>(d.nz, gz3, st, axis_args(slot0, na, slot1, 3, 0)));            // Z1
+    timer.end(ev, FWI_PASS_Z_MINUS, 6 * ns * S, st);
+    ev = timer.begin(st);
     FWI_HIP(launch_axis_y<T>(d.ny, true, gy3, st, axis_args(slot0, na, slot1, 3, 0)));       // Y2
+    timer.end(ev, FWI_PASS_Y_INV, 6 * ns * S, st);
     return FWI_OK;
   }
 
@@ -462,8 +549,20 @@ template <typename T> struct Engine : EngineBase {
     return a;
   }
   int launch_x2(int mode, int B, const X2Args<T>& a, hipStream_t st) {
-    const int lpb = x_lines_per_block<T>(d.M);
+    const int lpb = x_lines_per_block_den<T>(d.M);
+    const double S = sbytes(), F = fbytes(), t = sizeof(T);
+    hipEvent_t ev = (mode == XM_FWD || mode == XM_PAIR) ? timer.begin(st) : nullptr;
     FWI_HIP(launch_x_den<T>(d.M, mode, dim3((d.nlines + lpb - 1) / lpb, B), st, a));
+    if (mode == XM_FWD) {
+      // 3 spectra in, 1 out, split densities r/w, c0, source row, trace row, tape row
+      const double b = B * (4 * S + 7 * F + t * (d.n_src + d.n_rec + (a.tape ? d.n_bnd : 0)));
+      timer.end(ev, FWI_PASS_X_DEN_FWD, b, st);
+    } else if (mode == XM_PAIR) {
+      // two simulations of (4 S + 6 F), c0 once, adjoint source row, tape row,
+      // ring (2 reads + 1 write), FP64 accumulator read + write
+      const double b = B * (2 * (4 * S + 6 * F) + F + t * (d.n_rec + d.n_bnd + 3.0 * d.n_gam) + 16.0 * d.n_gam);
+      timer.end(ev, FWI_PASS_X_DEN_PAIR, b, st);
+    }
     return FWI_OK;
   }
 
@@ -514,6 +613,7 @@ template <typename T> struct Engine : EngineBase {
     X2Args<T> a = x2_args(B, c);
     a.src_sig = src; a.w = w; a.traces = traces; a.tape = save ? tape : nullptr;
     for (int n = 0; n < p.nt; ++n) {
+      timer.sample(n);
       if ((rc = step_spectral(tr0, B, tr0, B, st))) return rc;
       a.step = n;
       if ((rc = launch_x2(XM_FWD, B, a, st))) return rc;
@@ -556,6 +656,7 @@ template <typename T> struct Engine : EngineBase {
     }
     for (int j = 0; j < N; ++j) {
       const int k = j + 2;
+      timer.sample(j);
       a.step = j;
       a.ring_a = j % 3; a.ring_b = (j + 1) % 3; a.ring_c = k % 3;
       if (k <= N - 1) {
@@ -567,6 +668,7 @@ template <typename T> struct Engine : EngineBase {
         if ((rc = launch_x2(XM_ADJONLY, B, a, st))) return rc;
       }
     }
+    timer.active = false;
     // G on Gamma -> full grid, zero elsewhere
     if ((rc = fill<T>(grad, (long long)B * d.nfield, (T)0, st))) return rc;
     if (d.n_gam > 0) {
@@ -594,6 +696,7 @@ template <typename T> struct Engine : EngineBase {
     tape_valid = false;
     if ((rc = run_forward(B, (const T*)c, (const T*)src, w, (T*)traces, save, st))) return rc;
     if (save) { tape_valid = true; tape_B = B; }
+    FWI_HIP(timer.collect(st));
     if (flags & FWI_CHECK_FINITE)
       if ((rc = check_finite((const T*)traces, (long long)B * p.nt * d.n_rec, st))) return rc;
     return FWI_OK;
@@ -613,6 +716,7 @@ template <typename T> struct Engine : EngineBase {
     if ((rc = run_adjoint_tr(B, (const T*)c, (const T*)obs, false, traces_int, misfit, (T*)grad,
                              (flags & FWI_TR_FINAL_STATE) != 0, st)))
       return rc;
+    FWI_HIP(timer.collect(st));
     if (flags & FWI_CHECK_FINITE)
       if ((rc = check_finite((const T*)grad, (long long)B * d.nfield, st))) return rc;
     return FWI_OK;
@@ -628,6 +732,7 @@ template <typename T> struct Engine : EngineBase {
     if ((rc = run_adjoint_tr(B, (const T*)c, (const T*)resid, true, (const T*)resid, misfit, (T*)grad,
                              (flags & FWI_TR_FINAL_STATE) != 0, st)))
       return rc;
+    FWI_HIP(timer.collect(st));
     if (flags & FWI_CHECK_FINITE)
       if ((rc = check_finite((const T*)grad, (long long)B * d.nfield, st))) return rc;
     return FWI_OK;
@@ -737,6 +842,25 @@ int fwi_backward(fwi_handle* h, int32_t B, const void* c, const void* residual, 
 int fwi_derivative(fwi_handle* h, const void* in, void* out, int32_t axis, int32_t sign, fwi_stream_t stream) {
   if (!h) return fail(FWI_ERR_INVALID_ARG, "handle is NULL");
   return h->eng->derivative(in, out, axis, sign, (hipStream_t)stream);
+}
+
+int fwi_timing_enable(fwi_handle* h, int32_t every) {
+  if (!h || every < 0) return fail(FWI_ERR_INVALID_ARG, "bad arguments");
+  h->eng->timer.every = every;
+  return FWI_OK;
+}
+
+int fwi_timing_read(fwi_handle* h, int32_t pass, int64_t* launches, double* total_ms, double* total_bytes) {
+  if (!h || pass < 0 || pass >= FWI_PASS_COUNT || !launches || !total_ms || !total_bytes)
+    return fail(FWI_ERR_INVALID_ARG, "bad arguments");
+  PassTimer& t = h->eng->timer;
+  *launches = t.launches[pass];
+  *total_ms = t.ms[pass];
+  *total_bytes = t.bytes[pass];
+  t.launches[pass] = 0;
+  t.ms[pass] = 0;
+  t.bytes[pass] = 0;
+  return FWI_OK;
 }
 
 const char* fwi_status_string(int status) {

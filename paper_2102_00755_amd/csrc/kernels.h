@@ -26,21 +26,29 @@ namespace fwi {
 // ----------------------------------------------------------------------------
 // launch geometry
 // ----------------------------------------------------------------------------
-template <typename T> constexpr int axis_tw() { return 128 / (int)(2 * sizeof(T)); }
+// axis-pass tile width: 64-byte row segments (8 FP32 / 4 FP64 complex); measured
+// faster than 128-byte segments because twice as many tiles fit in LDS per CU
+template <typename T> constexpr int axis_tw() { return 64 / (int)(2 * sizeof(T)); }
 constexpr int axis_nt(int L, int TW) {
   int n = L * TW / 8;
   n = n < 64 ? 64 : (n > 256 ? 256 : n);
   return (n + 63) / 64 * 64;
 }
-// x-lines per workgroup of the x passes
-template <typename T> constexpr int x_lpb(int M) {
-  int l = 1024 / M;
-  if (l > 16) l = 16;
-  int p = 1;
-  while (p * 2 <= l) p *= 2;
-  if (sizeof(T) == 8 && p > 1) p /= 2;
-  return p;
+// x-lines per workgroup of the x passes.  LDS regions hold the lines as
+// columns without padding, so their column counts (LPB, 2 LPB, 3 LPB) must
+// keep 64-bit accesses conflict-free: an odd LPB gives odd or 2-mod-4
+// strides, measured conflict-free on gfx950 (strides with a factor of 4 and
+// gapped runs are not).
+template <typename T> constexpr int odd_lpb(int budget, int M) {
+  int l = budget / (M * (int)sizeof(T));
+  if (l > 15) l = 15;
+  if (l < 1) l = 1;
+  if ((l & 1) == 0) l -= 1;
+  return l;
 }
+template <typename T> constexpr int x_lpb_vel(int M) { return odd_lpb<T>(5120, M); }
+template <typename T> constexpr int x_lpb_den(int M) { return odd_lpb<T>(3072, M); }
+template <typename T> constexpr int x_lpb(int M) { return odd_lpb<T>(4096, M); }
 constexpr int X_NT = 256;
 
 // sinc(sqrt(u)) = sum_n (-1)^n u^n / (2n+1)!, n = 0..10 (accurate to double
@@ -82,23 +90,36 @@ __device__ __forceinline__ int slot_of(int i, int slot0, int na, int slot1) {
   return i < na ? slot0 + i : slot1 + (i - na);
 }
 
+// All global loads of a thread are issued before the first LDS store so that
+// the whole tile is in flight at once (memory-level parallelism is what
+// bounds a streaming pass).
 template <typename T, int L, int TW, int NT>
 __device__ __forceinline__ void tile_load(cplx<T>* buf, const cplx<T>* g, size_t rstride, int ncol) {
   using C = cplx<T>;
   constexpr int E = L * TW;
-#pragma unroll 4
-  for (int e = threadIdx.x; e < E; e += NT) {
+  constexpr int EPT = (E + NT - 1) / NT;
+  C tmp[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = (int)threadIdx.x + i * NT;
     const int r = e / TW, c = e % TW;
-    buf[e] = (c < ncol) ? g[(size_t)r * rstride + c] : cmake<C>((T)0, (T)0);
+    tmp[i] = (c < ncol && (E % NT == 0 || e < E)) ? g[(size_t)r * rstride + c] : cmake<C>((T)0, (T)0);
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = (int)threadIdx.x + i * NT;
+    if (E % NT == 0 || e < E) buf[e] = tmp[i];
   }
 }
 template <typename T, int L, int TW, int NT>
 __device__ __forceinline__ void tile_store(const cplx<T>* buf, cplx<T>* g, size_t rstride, int ncol) {
   constexpr int E = L * TW;
-#pragma unroll 4
-  for (int e = threadIdx.x; e < E; e += NT) {
+  constexpr int EPT = (E + NT - 1) / NT;
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = (int)threadIdx.x + i * NT;
     const int r = e / TW, c = e % TW;
-    if (c < ncol) g[(size_t)r * rstride + c] = buf[e];
+    if (c < ncol && (E % NT == 0 || e < E)) g[(size_t)r * rstride + c] = buf[e];
   }
 }
 
@@ -224,29 +245,44 @@ k_axis_z_plus(AxisArgs<T> a) {
 // ----------------------------------------------------------------------------
 // Load NREG spectra lines (M+1 complex each) of LPB lines into columns
 // [col0, col0 + NREG*LPB) of buf (rows 0..M).
-template <typename T, int M, int LPB, int TWP>
-__device__ __forceinline__ void x_load_spectra(cplx<T>* buf, cplx<T>* const* spec, int nreg, int col0,
-                                               int l0, int nl, size_t px) {
+template <typename T, int M, int LPB, int TWP, int NREG>
+__device__ __forceinline__ void x_load_spectra(cplx<T>* buf, cplx<T>* const* spec, int col0, int l0, int nl,
+                                               size_t px) {
   using C = cplx<T>;
-  const int per = (M + 1) * LPB;
-  for (int e = threadIdx.x; e < nreg * per; e += X_NT) {
-    const int f = e / per;
-    const int rem = e % per;
+  constexpr int PER = (M + 1) * LPB;
+  constexpr int E = NREG * PER;
+  constexpr int EPT = (E + X_NT - 1) / X_NT;
+  C tmp[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = (int)threadIdx.x + i * X_NT;
+    const int f = e / PER;
+    const int rem = e % PER;
     const int l = rem / (M + 1), k = rem % (M + 1);
-    C v = cmake<C>((T)0, (T)0);
-    if (l < nl) v = spec[f][(size_t)(l0 + l) * px + k];
-    buf[k * TWP + col0 + f * LPB + l] = v;
+    tmp[i] = (e < E && l < nl) ? spec[f][(size_t)(l0 + l) * px + k] : cmake<C>((T)0, (T)0);
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = (int)threadIdx.x + i * X_NT;
+    const int f = e / PER;
+    const int rem = e % PER;
+    const int l = rem / (M + 1), k = rem % (M + 1);
+    if (e < E) buf[k * TWP + col0 + f * LPB + l] = tmp[i];
   }
 }
-template <typename T, int M, int LPB, int TWP>
-__device__ __forceinline__ void x_store_spectra(const cplx<T>* buf, cplx<T>* const* spec, int nreg, int col0,
-                                                int l0, int nl, size_t px) {
-  const int per = (M + 1) * LPB;
-  for (int e = threadIdx.x; e < nreg * per; e += X_NT) {
-    const int f = e / per;
-    const int rem = e % per;
+template <typename T, int M, int LPB, int TWP, int NREG>
+__device__ __forceinline__ void x_store_spectra(const cplx<T>* buf, cplx<T>* const* spec, int col0, int l0,
+                                                int nl, size_t px) {
+  constexpr int PER = (M + 1) * LPB;
+  constexpr int E = NREG * PER;
+  constexpr int EPT = (E + X_NT - 1) / X_NT;
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = (int)threadIdx.x + i * X_NT;
+    const int f = e / PER;
+    const int rem = e % PER;
     const int l = rem / (M + 1), k = rem % (M + 1);
-    if (l < nl) spec[f][(size_t)(l0 + l) * px + k] = buf[k * TWP + col0 + f * LPB + l];
+    if (e < E && l < nl) spec[f][(size_t)(l0 + l) * px + k] = buf[k * TWP + col0 + f * LPB + l];
   }
 }
 
@@ -318,36 +354,48 @@ template <typename T> struct XArgs {
 template <typename T, int M>
 __global__ void __launch_bounds__(X_NT) k_x_velocity(XArgs<T> a) {
   using C = cplx<T>;
-  constexpr int LPB = x_lpb<T>(M);
+  constexpr int LPB = x_lpb_vel<T>(M);
   constexpr int NC = 3 * LPB;
-  constexpr int TWP = NC + 1;
+  constexpr int TWP = NC;
   __shared__ C buf[(M + 1) * TWP];
   const int l0 = blockIdx.x * LPB;
   const int nl = min(LPB, a.d.nlines - l0);
   const Slot<T> sl = a.slots[slot_of(blockIdx.y, a.slot0, a.na, a.slot1)];
   const size_t px = a.d.px;
-  x_load_spectra<T, M, LPB, TWP>(buf, sl.spec, 3, 0, l0, nl, px);
+  const int nx = a.d.nx;
+  // prefetch the velocities: in flight during the C2R transforms
+  constexpr int EB = (M * LPB + X_NT - 1) / X_NT;
+  C vv[EB][3];
+#pragma unroll
+  for (int i = 0; i < EB; ++i) {
+    const int e = (int)threadIdx.x + i * X_NT;
+    const int l = e / M, n = e % M;
+    const bool ok = (e < M * LPB) && (l < nl);
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+      vv[i][f] = ok ? reinterpret_cast<const C*>(sl.v[f] + (size_t)(l0 + l) * nx)[n] : cmake<C>((T)0, (T)0);
+  }
+  x_load_spectra<T, M, LPB, TWP, 3>(buf, sl.spec, 0, l0, nl, px);
   __syncthreads();
   c2r_pre<T, M, TWP, NC>(buf, a.tb.rtw);
   __syncthreads();
   lds_fft<T, M, NC, TWP, X_NT, true>(buf, a.tb.tw_x);
-  const int nx = a.d.nx;
-  for (int e = threadIdx.x; e < M * LPB; e += X_NT) {
+#pragma unroll
+  for (int i = 0; i < EB; ++i) {
+    const int e = (int)threadIdx.x + i * X_NT;
     const int l = e / M, n = e % M;
-    if (l >= nl) continue;
+    if (e >= M * LPB || l >= nl) continue;
     const int line = l0 + l;
     const int yy = line % a.d.ny, zz = line / a.d.ny;
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
       const C dp = buf[n * TWP + f * LPB + l];
-      C* vp = reinterpret_cast<C*>(sl.v[f] + (size_t)line * nx) + n;
-      const C vv = *vp;
       T lx, ly;
       if (f == 0) { lx = a.tb.pml_s[0][2 * n]; ly = a.tb.pml_s[0][2 * n + 1]; }
       else if (f == 1) { lx = ly = a.tb.pml_s[1][yy]; }
       else { lx = ly = a.tb.pml_s[2][zz]; }
-      const C vn = cmake<C>(lx * (lx * vv.x - a.dt_rho * dp.x), ly * (ly * vv.y - a.dt_rho * dp.y));
-      *vp = vn;
+      const C vn = cmake<C>(lx * (lx * vv[i][f].x - a.dt_rho * dp.x), ly * (ly * vv[i][f].y - a.dt_rho * dp.y));
+      reinterpret_cast<C*>(sl.v[f] + (size_t)line * nx)[n] = vn;
       buf[n * TWP + f * LPB + l] = vn;
     }
   }
@@ -355,7 +403,7 @@ __global__ void __launch_bounds__(X_NT) k_x_velocity(XArgs<T> a) {
   lds_fft<T, M, NC, TWP, X_NT, false>(buf, a.tb.tw_x);
   r2c_post<T, M, TWP, NC>(buf, a.tb.rtw);
   __syncthreads();
-  x_store_spectra<T, M, LPB, TWP>(buf, sl.spec, 3, 0, l0, nl, px);
+  x_store_spectra<T, M, LPB, TWP, 3>(buf, sl.spec, 0, l0, nl, px);
 }
 
 enum XMode { XM_FWD = 0, XM_PAIR = 1, XM_TRONLY = 2, XM_ADJONLY = 3 };
@@ -396,16 +444,30 @@ __device__ __forceinline__ int local_line(const int32_t* off, int l0, int nl, in
 // Density update of one simulation slot for the workgroup's lines: C2R of
 // d-_a v_a, rho_a <- L_a (L_a rho_a - dt rho0 d-_a v_a) (+ injection, or
 // Dirichlet on dGamma), p = c0^2 sum_a rho_a written to column pcol of buf.
-template <typename T, int M, int LPB, int TWP, int KIND>
+template <typename T, int M, int LPB, int TWP, int TWPP, int KIND>
 __device__ __forceinline__ void density_update(const X2Args<T>& a, const Slot<T>& sl, int b, int l0, int nl,
-                                               bool zero_state, int pcol, cplx<T>* buf, cplx<T>* spv,
-                                               uint8_t* spm) {
+                                               bool zero_state, int pcol, cplx<T>* buf, cplx<T>* bufp,
+                                               cplx<T>* spv, uint8_t* spm) {
   using C = cplx<T>;
   constexpr int NC = 3 * LPB;
   const int nx = a.d.nx;
   const size_t px = a.d.px;
   const T* cb = a.c + (size_t)b * a.d.nfield;
-  if (!zero_state) x_load_spectra<T, M, LPB, TWP>(buf, sl.spec, 3, 0, l0, nl, px);
+  // prefetch c0 and the split densities: in flight during the C2R transforms
+  constexpr int EB = (M * LPB + X_NT - 1) / X_NT;
+  C cc[EB], rr[EB][3];
+#pragma unroll
+  for (int i = 0; i < EB; ++i) {
+    const int e = (int)threadIdx.x + i * X_NT;
+    const int l = e / M, n = e % M;
+    const bool ok = (e < M * LPB) && (l < nl);
+    const size_t lo = (size_t)(l0 + l) * nx;
+    cc[i] = ok ? reinterpret_cast<const C*>(cb + lo)[n] : cmake<C>((T)0, (T)0);
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+      rr[i][f] = (ok && !zero_state) ? reinterpret_cast<const C*>(sl.rho[f] + lo)[n] : cmake<C>((T)0, (T)0);
+  }
+  if (!zero_state) x_load_spectra<T, M, LPB, TWP, 3>(buf, sl.spec, 0, l0, nl, px);
   for (int e = threadIdx.x; e < M * LPB; e += X_NT) {
     spv[e] = cmake<C>((T)0, (T)0);
     if (KIND == SP_DIRICHLET) { spm[2 * e] = 0; spm[2 * e + 1] = 0; }
@@ -453,12 +515,14 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const Slot<T>
   } else {
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < M * LPB; e += X_NT) {
+#pragma unroll
+  for (int i = 0; i < EB; ++i) {
+    const int e = (int)threadIdx.x + i * X_NT;
     const int l = e / M, n = e % M;
-    if (l >= nl) continue;
+    if (e >= M * LPB || l >= nl) continue;
     const int line = l0 + l;
     const int yy = line % a.d.ny, zz = line / a.d.ny;
-    const C c2 = *(reinterpret_cast<const C*>(cb + (size_t)line * nx) + n);
+    const C c2 = cc[i];
     const C sv = spv[n * LPB + l];
     C sum = cmake<C>((T)0, (T)0);
 #pragma unroll
@@ -469,12 +533,11 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const Slot<T>
         rn = cmake<C>((T)0, (T)0);
       } else {
         const C dv = buf[n * TWP + f * LPB + l];
-        const C rr = *rp;
         T lx, ly;
         if (f == 0) { lx = a.tb.pml_n[0][2 * n]; ly = a.tb.pml_n[0][2 * n + 1]; }
         else if (f == 1) { lx = ly = a.tb.pml_n[1][yy]; }
         else { lx = ly = a.tb.pml_n[2][zz]; }
-        rn = cmake<C>(lx * (lx * rr.x - a.dt_rho0 * dv.x), ly * (ly * rr.y - a.dt_rho0 * dv.y));
+        rn = cmake<C>(lx * (lx * rr[i][f].x - a.dt_rho0 * dv.x), ly * (ly * rr[i][f].y - a.dt_rho0 * dv.y));
       }
       if (KIND == SP_DIRICHLET) {
         if (spm[2 * (n * LPB + l)]) rn.x = sv.x;
@@ -485,15 +548,15 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const Slot<T>
       *rp = rn;
       sum = cadd(sum, rn);
     }
-    buf[n * TWP + pcol + l] = cmake<C>(c2.x * c2.x * sum.x, c2.y * c2.y * sum.y);
+    bufp[n * TWPP + pcol + l] = cmake<C>(c2.x * c2.x * sum.x, c2.y * c2.y * sum.y);
   }
   __syncthreads();
 }
 
 // read p at voxel x of local line l from the packed column pcol
-template <typename T, int TWP>
-__device__ __forceinline__ T p_at(const cplx<T>* buf, int pcol, int l, int x) {
-  const cplx<T> z = buf[(x >> 1) * TWP + pcol + l];
+template <typename T, int TWPP>
+__device__ __forceinline__ T p_at(const cplx<T>* bufp, int pcol, int l, int x) {
+  const cplx<T> z = bufp[(x >> 1) * TWPP + pcol + l];
   return (x & 1) ? z.y : z.x;
 }
 
@@ -507,11 +570,12 @@ __device__ __forceinline__ T p_at(const cplx<T>* buf, int pcol, int l, int x) {
 template <typename T, int M, int MODE>
 __global__ void __launch_bounds__(X_NT) k_x_density(X2Args<T> a) {
   using C = cplx<T>;
-  constexpr int LPB = x_lpb<T>(M);
+  constexpr int LPB = x_lpb_den<T>(M);
   constexpr int NP = (MODE == XM_PAIR) ? 2 : 1;
-  constexpr int NC = (3 + NP) * LPB;
-  constexpr int TWP = NC + 1;
+  constexpr int TWP = 3 * LPB;        // d-_a v_a of the three axes
+  constexpr int TWPP = NP * LPB;      // new pressure(s), packed for the R2C
   __shared__ C buf[(M + 1) * TWP];
+  __shared__ C bufp[(M + 1) * TWPP];
   __shared__ C spv[M * LPB];
   __shared__ uint8_t spm[(MODE == XM_PAIR || MODE == XM_TRONLY) ? 2 * M * LPB : 1];
   const int l0 = blockIdx.x * LPB;
@@ -519,36 +583,35 @@ __global__ void __launch_bounds__(X_NT) k_x_density(X2Args<T> a) {
   const int b = blockIdx.y;
   const int nx = a.d.nx;
   const size_t px = a.d.px;
-  const int PA = 3 * LPB;               // column of the adjoint / forward pressure
-  const int PT = (NP == 2) ? 4 * LPB : 3 * LPB;  // column of the TR pressure
+  const int PA = 0;                         // column of the adjoint / forward pressure
+  const int PT = (NP == 2) ? LPB : 0;       // column of the TR pressure
   const Slot<T> s_adj = a.slots[b];
   const Slot<T> s_tr = a.slots[a.tr_off + b];
 
   if (MODE == XM_FWD) {
-    density_update<T, M, LPB, TWP, SP_SOURCE>(a, s_tr, b, l0, nl, false, PA, buf, spv, spm);
+    density_update<T, M, LPB, TWP, TWPP, SP_SOURCE>(a, s_tr, b, l0, nl, false, PA, buf, bufp, spv, spm);
     // sensors f^n = M p and boundary tape g^n = p(dGamma)
-    {
-      const int i0 = a.g.rec_off[l0], i1 = a.g.rec_off[l0 + nl];
-      for (int i = i0 + (int)threadIdx.x; i < i1; i += X_NT) {
-        const int l = local_line(a.g.rec_off, l0, nl, i);
-        a.traces[((size_t)b * a.d.nt + a.step) * a.d.n_rec + a.g.rec_id[i]] =
-            p_at<T, TWP>(buf, PA, l, a.g.rec_x[i]);
-      }
-      if (a.tape) {
-        const int j0 = a.g.bnd_off[l0], j1 = a.g.bnd_off[l0 + nl];
-        T* trow = a.tape + ((size_t)b * a.d.nt + a.step) * a.d.n_bnd;
-        for (int i = j0 + (int)threadIdx.x; i < j1; i += X_NT) {
-          const int l = local_line(a.g.bnd_off, l0, nl, i);
-          trow[i] = p_at<T, TWP>(buf, PA, l, a.g.bnd_x[i]);
-        }
+    const int i0 = a.g.rec_off[l0], i1 = a.g.rec_off[l0 + nl];
+    for (int i = i0 + (int)threadIdx.x; i < i1; i += X_NT) {
+      const int l = local_line(a.g.rec_off, l0, nl, i);
+      a.traces[((size_t)b * a.d.nt + a.step) * a.d.n_rec + a.g.rec_id[i]] =
+          p_at<T, TWPP>(bufp, PA, l, a.g.rec_x[i]);
+    }
+    if (a.tape) {
+      const int j0 = a.g.bnd_off[l0], j1 = a.g.bnd_off[l0 + nl];
+      T* trow = a.tape + ((size_t)b * a.d.nt + a.step) * a.d.n_bnd;
+      for (int i = j0 + (int)threadIdx.x; i < j1; i += X_NT) {
+        const int l = local_line(a.g.bnd_off, l0, nl, i);
+        trow[i] = p_at<T, TWPP>(bufp, PA, l, a.g.bnd_x[i]);
       }
     }
   }
   if (MODE == XM_PAIR || MODE == XM_ADJONLY) {
-    density_update<T, M, LPB, TWP, SP_ADJOINT>(a, s_adj, b, l0, nl, false, PA, buf, spv, spm);
+    density_update<T, M, LPB, TWP, TWPP, SP_ADJOINT>(a, s_adj, b, l0, nl, false, PA, buf, bufp, spv, spm);
   }
   if (MODE == XM_PAIR || MODE == XM_TRONLY) {
-    density_update<T, M, LPB, TWP, SP_DIRICHLET>(a, s_tr, b, l0, nl, a.tr_zero_state != 0, PT, buf, spv, spm);
+    density_update<T, M, LPB, TWP, TWPP, SP_DIRICHLET>(a, s_tr, b, l0, nl, a.tr_zero_state != 0, PT, buf, bufp,
+                                                       spv, spm);
   }
   if (MODE != XM_FWD) {
     // ring update and gradient: G += 2/c0^3 p_adj (p_tr^(j) - 2 p_tr^(j+1) + p_tr^(j+2))
@@ -561,9 +624,9 @@ __global__ void __launch_bounds__(X_NT) k_x_density(X2Args<T> a) {
       const int x = a.g.gam_x[i];
       // p_tr^(k) = 0 for k >= N: the ring slot is written in every mode so
       // that the next iteration never reads a stale entry
-      const T ptr = (MODE == XM_ADJONLY) ? (T)0 : p_at<T, TWP>(buf, PT, l, x);
+      const T ptr = (MODE == XM_ADJONLY) ? (T)0 : p_at<T, TWPP>(bufp, PT, l, x);
       if (MODE != XM_TRONLY) {
-        const T padj = p_at<T, TWP>(buf, PA, l, x);
+        const T padj = p_at<T, TWPP>(bufp, PA, l, x);
         const T cv = cb[(size_t)(l0 + l) * nx + x];
         const T pm = ring[(size_t)a.ring_a * a.d.n_gam + i];
         const T p0 = ring[(size_t)a.ring_b * a.d.n_gam + i];
@@ -575,21 +638,15 @@ __global__ void __launch_bounds__(X_NT) k_x_density(X2Args<T> a) {
   }
   __syncthreads();
   // forward x-transform of the new pressure(s)
-  {
-    cplx<T>* pa_spec[1] = {(MODE == XM_TRONLY || MODE == XM_FWD) ? s_tr.spec[0] : s_adj.spec[0]};
-    const int c0 = (MODE == XM_TRONLY) ? PT : PA;
-    if (NP == 2) {
-      lds_fft<T, M, 2 * LPB, TWP, X_NT, false>(buf + PA, a.tb.tw_x);
-      r2c_post<T, M, TWP, 2 * LPB>(buf + PA, a.tb.rtw);
-      __syncthreads();
-      cplx<T>* specs[2] = {s_adj.spec[0], s_tr.spec[0]};
-      x_store_spectra<T, M, LPB, TWP>(buf, specs, 2, PA, l0, nl, px);
-    } else {
-      lds_fft<T, M, LPB, TWP, X_NT, false>(buf + c0, a.tb.tw_x);
-      r2c_post<T, M, TWP, LPB>(buf + c0, a.tb.rtw);
-      __syncthreads();
-      x_store_spectra<T, M, LPB, TWP>(buf, pa_spec, 1, c0, l0, nl, px);
-    }
+  lds_fft<T, M, TWPP, TWPP, X_NT, false>(bufp, a.tb.tw_x);
+  r2c_post<T, M, TWPP, TWPP>(bufp, a.tb.rtw);
+  __syncthreads();
+  if (NP == 2) {
+    cplx<T>* specs[2] = {s_adj.spec[0], s_tr.spec[0]};
+    x_store_spectra<T, M, LPB, TWPP, 2>(bufp, specs, 0, l0, nl, px);
+  } else {
+    cplx<T>* specs[1] = {(MODE == XM_TRONLY || MODE == XM_FWD) ? s_tr.spec[0] : s_adj.spec[0]};
+    x_store_spectra<T, M, LPB, TWPP, 1>(bufp, specs, 0, l0, nl, px);
   }
 }
 
@@ -672,7 +729,7 @@ template <typename T, int M>
 __global__ void __launch_bounds__(X_NT) k_x_r2c(XArgs<T> a, const T* in, int f) {
   using C = cplx<T>;
   constexpr int LPB = x_lpb<T>(M);
-  constexpr int TWP = LPB + 1;
+  constexpr int TWP = LPB;
   __shared__ C buf[(M + 1) * TWP];
   const int l0 = blockIdx.x * LPB;
   const int nl = min(LPB, a.d.nlines - l0);
@@ -687,20 +744,20 @@ __global__ void __launch_bounds__(X_NT) k_x_r2c(XArgs<T> a, const T* in, int f) 
   r2c_post<T, M, TWP, LPB>(buf, a.tb.rtw);
   __syncthreads();
   cplx<T>* specs[1] = {sl.spec[f]};
-  x_store_spectra<T, M, LPB, TWP>(buf, specs, 1, 0, l0, nl, a.d.px);
+  x_store_spectra<T, M, LPB, TWP, 1>(buf, specs, 0, l0, nl, a.d.px);
 }
 
 template <typename T, int M>
 __global__ void __launch_bounds__(X_NT) k_x_c2r(XArgs<T> a, T* out, int f) {
   using C = cplx<T>;
   constexpr int LPB = x_lpb<T>(M);
-  constexpr int TWP = LPB + 1;
+  constexpr int TWP = LPB;
   __shared__ C buf[(M + 1) * TWP];
   const int l0 = blockIdx.x * LPB;
   const int nl = min(LPB, a.d.nlines - l0);
   const Slot<T> sl = a.slots[a.slot0];
   cplx<T>* specs[1] = {sl.spec[f]};
-  x_load_spectra<T, M, LPB, TWP>(buf, specs, 1, 0, l0, nl, a.d.px);
+  x_load_spectra<T, M, LPB, TWP, 1>(buf, specs, 0, l0, nl, a.d.px);
   __syncthreads();
   c2r_pre<T, M, TWP, LPB>(buf, a.tb.rtw);
   __syncthreads();

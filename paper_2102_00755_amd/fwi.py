@@ -185,3 +185,20 @@ class Handle:
         _check(self._lib.fwi_derivative(self._h, f.data_ptr(), out.data_ptr(), int(axis), int(sign),
                                         self._stream()), "fwi_derivative")
         return out
+
+    # ------------------------------------------------------------------
+    def timing_enable(self, every: int) -> None:
+        """Sample every `every`-th time step's pass launches with HIP events."""
+        _check(self._lib.fwi_timing_enable(self._h, int(every)), "fwi_timing_enable")
+
+    def timing_read(self) -> dict:
+        """{pass name: (sampled launches, total ms, total algorithmic bytes)}; resets."""
+        out = {}
+        for k, name in enumerate(L.PASS_NAMES):
+            n = ctypes.c_int64()
+            ms = ctypes.c_double()
+            by = ctypes.c_double()
+            _check(self._lib.fwi_timing_read(self._h, k, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)),
+                   "fwi_timing_read")
+            out[name] = (int(n.value), float(ms.value), float(by.value))
+        return out

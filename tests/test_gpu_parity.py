@@ -1,7 +1,7 @@
 """GPU parity: the HIP path through the C-ABI against the FP64 oracle.
 
 Sizes span several tiles with a ragged tail (the half spectrum along x has
-nx/2 + 1 columns; axis tiles are 16 (FP32) / 8 (FP64) columns wide) and the
+nx/2 + 1 columns; axis tiles are 8 (FP32) / 4 (FP64) columns wide) and the
 radices 2, 3, 4, 5, 7, 8.  Tolerances: FP64 builds at round-off level; FP32
 rel l2 <= 1e-4 on traces and <= 1e-3 on gradients.
 """
