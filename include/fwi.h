@@ -58,8 +58,11 @@ enum {
   FWI_SAVE_TAPE = 1,    /* forward keeps the dGamma tape for fwi_backward     */
   FWI_CHECK_INPUT = 2,  /* validate c in [c_min, c_max] (reads a flag back)   */
   FWI_CHECK_FINITE = 4, /* check outputs are finite (reads a flag back)       */
-  FWI_TR_FINAL_STATE = 8 /* start the TR run from the final forward state
-                            instead of the paper's zero interior            */
+  FWI_TR_FINAL_STATE = 8, /* start the TR run from the final forward state
+                             instead of the paper's zero interior           */
+  FWI_GRAPH = 16          /* capture one time step in a hipGraph and replay it
+                             (step index read from device memory); results
+                             are identical to eager launches                 */
 };
 
 /* Scheme parameters (App. B).  dt = cfl dx / c_max in the paper (Sec. 4.1). */

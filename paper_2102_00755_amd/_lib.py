@@ -25,6 +25,7 @@ FWI_SAVE_TAPE = 1
 FWI_CHECK_INPUT = 2
 FWI_CHECK_FINITE = 4
 FWI_TR_FINAL_STATE = 8
+FWI_GRAPH = 16
 
 SUPPORTED_LENGTHS = (8, 12, 16, 24, 32, 40, 48, 56, 64, 80, 96, 112, 128, 160, 224, 256, 448)
 

@@ -319,6 +319,8 @@ template <typename T> struct Engine : EngineBase {
   double* partial = nullptr;
   int32_t* gam_lin = nullptr;
   int* flag = nullptr;
+  int* step_counter = nullptr;   // device step index of replayed step graphs
+  bool use_graph = false;
   int nblk_rec = 1;
   bool tape_valid = false;
   int tape_B = 0;
@@ -363,6 +365,7 @@ template <typename T> struct Engine : EngineBase {
     gacc = (double*)mem_gacc.p;
     partial = (double*)mem_partial.p;
     flag = (int*)mem_flag.p;
+    step_counter = flag + 16;
     // slots: [v0 v1 v2 rho0 rho1 rho2 | spec0 spec1 spec2], 2*batch of them
     slots_host.resize(2 * p.batch);
     char* base = (char*)mem_slots.p;
@@ -605,6 +608,43 @@ template <typename T> struct Engine : EngineBase {
     return FWI_OK;
   }
 
+  // Capture body() (the launches of one time step) into a graph and replay
+  // it `count` times on st.  The step counter must be set before.
+  template <typename F> int replay_graph(F body, int count, hipStream_t st) {
+    if (count <= 0) return FWI_OK;
+    if (st == nullptr) return fail(FWI_ERR_INVALID_ARG, "FWI_GRAPH needs a non-null stream (capture)");
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    const bool was = timer.every > 0;
+    const int every = timer.every;
+    timer.every = 0;  // no event records inside a capture
+    timer.active = false;
+    FWI_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    int rc = body();
+    hipError_t e = hipStreamEndCapture(st, &g);
+    timer.every = was ? every : 0;
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(FWI_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return fail(FWI_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    for (int i = 0; i < count && e == hipSuccess; ++i) e = hipGraphLaunch(ge, st);
+    (void)hipGraphExecDestroy(ge);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(FWI_ERR_HIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+    return FWI_OK;
+  }
+  int count_step(hipStream_t st) {
+    hipLaunchKernelGGL(k_step_count, dim3(1), dim3(64), 0, st, step_counter);
+    FWI_HIP(hipGetLastError());
+    return FWI_OK;
+  }
+
   // --- Alg. 1 forward iteration ------------------------------------------
   int run_forward(int B, const T* c, const T* src, const int8_t* w, T* traces, bool save, hipStream_t st) {
     const int tr0 = p.batch;
@@ -612,6 +652,16 @@ template <typename T> struct Engine : EngineBase {
     if ((rc = zero_slots(tr0, B, st))) return rc;   // p^0 = 0, v = 0, rho = 0
     X2Args<T> a = x2_args(B, c);
     a.src_sig = src; a.w = w; a.traces = traces; a.tape = save ? tape : nullptr;
+    if (use_graph) {
+      if ((rc = fill<int>(step_counter, 1, 0, st))) return rc;
+      a.step_dev = step_counter;
+      return replay_graph([&]() -> int {
+        int r;
+        if ((r = step_spectral(tr0, B, tr0, B, st))) return r;
+        if ((r = launch_x2(XM_FWD, B, a, st))) return r;
+        return count_step(st);
+      }, p.nt, st);
+    }
     for (int n = 0; n < p.nt; ++n) {
       timer.sample(n);
       if ((rc = step_spectral(tr0, B, tr0, B, st))) return rc;
@@ -654,7 +704,21 @@ template <typename T> struct Engine : EngineBase {
       a.tape_row = N - 2; a.ring_c = 1;
       if ((rc = launch_x2(XM_TRONLY, B, a, st))) return rc;
     }
-    for (int j = 0; j < N; ++j) {
+    int j0 = 0;
+    if (use_graph && N >= 3) {   // iterations j = 0 .. N-3 pair with TR steps 2 .. N-1
+      if ((rc = fill<int>(step_counter, 1, 0, st))) return rc;
+      X2Args<T> ag = a;
+      ag.step_dev = step_counter;
+      if ((rc = replay_graph([&]() -> int {
+             int r;
+             if ((r = step_spectral(0, B, tr0, 2 * B, st))) return r;
+             if ((r = launch_x2(XM_PAIR, B, ag, st))) return r;
+             return count_step(st);
+           }, N - 2, st)))
+        return rc;
+      j0 = N - 2;
+    }
+    for (int j = j0; j < N; ++j) {
       const int k = j + 2;
       timer.sample(j);
       a.step = j;
@@ -693,6 +757,7 @@ template <typename T> struct Engine : EngineBase {
     if (flags & FWI_CHECK_INPUT)
       if ((rc = check_c(B, (const T*)c, st))) return rc;
     const bool save = (flags & FWI_SAVE_TAPE) != 0;
+    use_graph = (flags & FWI_GRAPH) != 0;
     tape_valid = false;
     if ((rc = run_forward(B, (const T*)c, (const T*)src, w, (T*)traces, save, st))) return rc;
     if (save) { tape_valid = true; tape_B = B; }
@@ -712,6 +777,7 @@ template <typename T> struct Engine : EngineBase {
     if (flags & FWI_CHECK_INPUT)
       if ((rc = check_c(B, (const T*)c, st))) return rc;
     tape_valid = false;
+    use_graph = (flags & FWI_GRAPH) != 0;
     if ((rc = run_forward(B, (const T*)c, (const T*)src, w, traces_int, true, st))) return rc;
     if ((rc = run_adjoint_tr(B, (const T*)c, (const T*)obs, false, traces_int, misfit, (T*)grad,
                              (flags & FWI_TR_FINAL_STATE) != 0, st)))
@@ -729,6 +795,7 @@ template <typename T> struct Engine : EngineBase {
     if (!c || !resid || !misfit || !grad) return fail(FWI_ERR_INVALID_ARG, "NULL array argument");
     if (!tape_valid || tape_B != B) return fail(FWI_ERR_NO_TAPE, "no saved tape for this batch size");
     FWI_HIP(hipSetDevice(device));
+    use_graph = (flags & FWI_GRAPH) != 0;
     if ((rc = run_adjoint_tr(B, (const T*)c, (const T*)resid, true, (const T*)resid, misfit, (T*)grad,
                              (flags & FWI_TR_FINAL_STATE) != 0, st)))
       return rc;

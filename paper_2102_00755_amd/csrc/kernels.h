@@ -429,7 +429,36 @@ template <typename T> struct X2Args {
   T* ring;               // [B][3][n_gam]
   int ring_a, ring_b, ring_c;
   double* gacc;          // [B][n_gam]
+  // When non-null the step index is read from device memory (replayed graph
+  // of one time step); tape row and ring slots then follow from it.
+  const int* step_dev;
 };
+
+// Per-launch step indices of an X2 launch.
+struct StepIdx {
+  int step, tape_row, ra, rb, rc;
+};
+
+template <typename T, int MODE>
+__device__ __forceinline__ StepIdx step_indices(const X2Args<T>& a) {
+  StepIdx s{a.step, a.tape_row, a.ring_a, a.ring_b, a.ring_c};
+  if (a.step_dev) {
+    const int j = *a.step_dev;
+    s.step = j;
+    if (MODE == XM_PAIR) {   // adjoint iteration j pairs with TR step k = j + 2
+      s.tape_row = a.d.nt - 3 - j;
+      s.ra = j % 3;
+      s.rb = (j + 1) % 3;
+      s.rc = (j + 2) % 3;
+    }
+  }
+  return s;
+}
+
+// advance the device step counter of a replayed time-step graph
+static __global__ void k_step_count(int* counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] += 1;
+}
 
 enum SpKind { SP_SOURCE = 0, SP_ADJOINT = 1, SP_DIRICHLET = 2 };
 
@@ -445,9 +474,9 @@ __device__ __forceinline__ int local_line(const int32_t* off, int l0, int nl, in
 // d-_a v_a, rho_a <- L_a (L_a rho_a - dt rho0 d-_a v_a) (+ injection, or
 // Dirichlet on dGamma), p = c0^2 sum_a rho_a written to column pcol of buf.
 template <typename T, int M, int LPB, int TWP, int TWPP, int KIND>
-__device__ __forceinline__ void density_update(const X2Args<T>& a, const Slot<T>& sl, int b, int l0, int nl,
-                                               bool zero_state, int pcol, cplx<T>* buf, cplx<T>* bufp,
-                                               cplx<T>* spv, uint8_t* spm) {
+__device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx& si, const Slot<T>& sl, int b,
+                                               int l0, int nl, bool zero_state, int pcol, cplx<T>* buf,
+                                               cplx<T>* bufp, cplx<T>* spv, uint8_t* spm) {
   using C = cplx<T>;
   constexpr int NC = 3 * LPB;
   const int nx = a.d.nx;
@@ -481,7 +510,7 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const Slot<T>
       const int x = a.g.src_x[i], id = a.g.src_id[i];
       const T cv = cb[(size_t)(l0 + l) * nx + x];
       const T val = a.src_k / cv * (T)a.w[(size_t)b * a.d.n_src + id] *
-                    a.src_sig[((size_t)b * a.d.nt + a.step) * a.d.n_src + id];
+                    a.src_sig[((size_t)b * a.d.nt + si.step) * a.d.n_src + id];
       T* sp = reinterpret_cast<T*>(spv);
       sp[2 * ((x >> 1) * LPB + l) + (x & 1)] = val;
     }
@@ -490,13 +519,13 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const Slot<T>
     for (int i = i0 + (int)threadIdx.x; i < i1; i += X_NT) {
       const int l = local_line(a.g.rec_off, l0, nl, i);
       const int x = a.g.rec_x[i], id = a.g.rec_id[i];
-      const T val = a.adj_src[((size_t)b * a.d.nt + a.step) * a.d.n_rec + id] * (T)(1.0 / 3.0);
+      const T val = a.adj_src[((size_t)b * a.d.nt + si.step) * a.d.n_rec + id] * (T)(1.0 / 3.0);
       T* sp = reinterpret_cast<T*>(spv);
       sp[2 * ((x >> 1) * LPB + l) + (x & 1)] = val;
     }
   } else {
     const int i0 = a.g.bnd_off[l0], i1 = a.g.bnd_off[l0 + nl];
-    const T* trow = a.tape + ((size_t)b * a.d.nt + a.tape_row) * a.d.n_bnd;
+    const T* trow = a.tape + ((size_t)b * a.d.nt + si.tape_row) * a.d.n_bnd;
     for (int i = i0 + (int)threadIdx.x; i < i1; i += X_NT) {
       const int l = local_line(a.g.bnd_off, l0, nl, i);
       const int x = a.g.bnd_x[i];
@@ -587,19 +616,20 @@ __global__ void __launch_bounds__(X_NT) k_x_density(X2Args<T> a) {
   const int PT = (NP == 2) ? LPB : 0;       // column of the TR pressure
   const Slot<T> s_adj = a.slots[b];
   const Slot<T> s_tr = a.slots[a.tr_off + b];
+  const StepIdx si = step_indices<T, MODE>(a);
 
   if (MODE == XM_FWD) {
-    density_update<T, M, LPB, TWP, TWPP, SP_SOURCE>(a, s_tr, b, l0, nl, false, PA, buf, bufp, spv, spm);
+    density_update<T, M, LPB, TWP, TWPP, SP_SOURCE>(a, si, s_tr, b, l0, nl, false, PA, buf, bufp, spv, spm);
     // sensors f^n = M p and boundary tape g^n = p(dGamma)
     const int i0 = a.g.rec_off[l0], i1 = a.g.rec_off[l0 + nl];
     for (int i = i0 + (int)threadIdx.x; i < i1; i += X_NT) {
       const int l = local_line(a.g.rec_off, l0, nl, i);
-      a.traces[((size_t)b * a.d.nt + a.step) * a.d.n_rec + a.g.rec_id[i]] =
+      a.traces[((size_t)b * a.d.nt + si.step) * a.d.n_rec + a.g.rec_id[i]] =
           p_at<T, TWPP>(bufp, PA, l, a.g.rec_x[i]);
     }
     if (a.tape) {
       const int j0 = a.g.bnd_off[l0], j1 = a.g.bnd_off[l0 + nl];
-      T* trow = a.tape + ((size_t)b * a.d.nt + a.step) * a.d.n_bnd;
+      T* trow = a.tape + ((size_t)b * a.d.nt + si.step) * a.d.n_bnd;
       for (int i = j0 + (int)threadIdx.x; i < j1; i += X_NT) {
         const int l = local_line(a.g.bnd_off, l0, nl, i);
         trow[i] = p_at<T, TWPP>(bufp, PA, l, a.g.bnd_x[i]);
@@ -607,10 +637,10 @@ __global__ void __launch_bounds__(X_NT) k_x_density(X2Args<T> a) {
     }
   }
   if (MODE == XM_PAIR || MODE == XM_ADJONLY) {
-    density_update<T, M, LPB, TWP, TWPP, SP_ADJOINT>(a, s_adj, b, l0, nl, false, PA, buf, bufp, spv, spm);
+    density_update<T, M, LPB, TWP, TWPP, SP_ADJOINT>(a, si, s_adj, b, l0, nl, false, PA, buf, bufp, spv, spm);
   }
   if (MODE == XM_PAIR || MODE == XM_TRONLY) {
-    density_update<T, M, LPB, TWP, TWPP, SP_DIRICHLET>(a, s_tr, b, l0, nl, a.tr_zero_state != 0, PT, buf, bufp,
+    density_update<T, M, LPB, TWP, TWPP, SP_DIRICHLET>(a, si, s_tr, b, l0, nl, a.tr_zero_state != 0, PT, buf, bufp,
                                                        spv, spm);
   }
   if (MODE != XM_FWD) {
@@ -628,12 +658,12 @@ __global__ void __launch_bounds__(X_NT) k_x_density(X2Args<T> a) {
       if (MODE != XM_TRONLY) {
         const T padj = p_at<T, TWPP>(bufp, PA, l, x);
         const T cv = cb[(size_t)(l0 + l) * nx + x];
-        const T pm = ring[(size_t)a.ring_a * a.d.n_gam + i];
-        const T p0 = ring[(size_t)a.ring_b * a.d.n_gam + i];
+        const T pm = ring[(size_t)si.ra * a.d.n_gam + i];
+        const T p0 = ring[(size_t)si.rb * a.d.n_gam + i];
         const T inc = (T)2 / (cv * cv * cv) * padj * (pm - (T)2 * p0 + ptr);
         gacc[i] += (double)inc;
       }
-      ring[(size_t)a.ring_c * a.d.n_gam + i] = ptr;
+      ring[(size_t)si.rc * a.d.n_gam + i] = ptr;
     }
   }
   __syncthreads();

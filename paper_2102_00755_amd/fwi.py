@@ -106,6 +106,9 @@ class Handle:
         self.n_src = geo.src.shape[0]
         self.n_rec = geo.rec.shape[0]
         p = _params(shape, dx, dt, nt, c_ref, c_min, c_max, rho0, pml, pml_alpha, precision, batch)
+        self.n_cells = self.shape[0] * self.shape[1] * self.shape[2]
+        self.tape_token = 0   # bumps whenever a call overwrites the saved tape
+        self.use_graph = False
         with torch.cuda.device(self.device):
             _check(self._lib.fwi_create(ctypes.byref(p), ctypes.byref(geo.c), int(device),
                                         ctypes.byref(self._h)), "fwi_create")
@@ -146,6 +149,8 @@ class Handle:
         w = self._t(w, (self.n_src,), torch.int8)
         tr = torch.empty((B, self.nt, self.n_rec), device=self.device, dtype=self.dtype)
         flags = (L.FWI_SAVE_TAPE if save_tape else 0) | (L.FWI_CHECK_INPUT if check else 0)
+        flags |= L.FWI_GRAPH if self.use_graph else 0
+        self.tape_token += 1
         _check(self._lib.fwi_forward(self._h, B, c.data_ptr(), src.data_ptr(), w.data_ptr(),
                                      tr.data_ptr(), flags, self._stream()), "fwi_forward")
         return tr
@@ -158,8 +163,14 @@ class Handle:
         w = self._t(w, (self.n_src,), torch.int8)
         obs = self._t(obs, (self.nt, self.n_rec))
         mis = torch.empty((B,), device=self.device, dtype=torch.float64)
-        grad = out if out is not None else torch.empty((B, *self.shape), device=self.device, dtype=self.dtype)
-        flags = L.FWI_CHECK_INPUT if check else 0
+        if out is not None:
+            if tuple(out.shape) != (B, *self.shape) or out.dtype != self.dtype or not out.is_contiguous():
+                raise ValueError("out must be a contiguous [B, nz, ny, nx] tensor of the handle's dtype")
+            grad = out
+        else:
+            grad = torch.empty((B, *self.shape), device=self.device, dtype=self.dtype)
+        flags = (L.FWI_CHECK_INPUT if check else 0) | (L.FWI_GRAPH if self.use_graph else 0)
+        self.tape_token += 1
         _check(self._lib.fwi_gradient(self._h, B, c.data_ptr(), src.data_ptr(), w.data_ptr(), obs.data_ptr(),
                                       mis.data_ptr(), grad.data_ptr(), flags, self._stream()), "fwi_gradient")
         return mis, grad
@@ -172,8 +183,9 @@ class Handle:
         r = self._t(residual, (self.nt, self.n_rec))
         mis = torch.empty((B,), device=self.device, dtype=torch.float64)
         grad = torch.empty((B, *self.shape), device=self.device, dtype=self.dtype)
+        flags = L.FWI_GRAPH if self.use_graph else 0
         _check(self._lib.fwi_backward(self._h, B, c.data_ptr(), r.data_ptr(), mis.data_ptr(), grad.data_ptr(),
-                                      0, self._stream()), "fwi_backward")
+                                      flags, self._stream()), "fwi_backward")
         return mis, grad
 
     def derivative(self, field, axis: int, sign: int):

@@ -1,0 +1,155 @@
+"""GPU tests of the system forms around the kernels and of the tiny
+FP64 configuration: hipGraph replay, autograd backward, serving mix."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import kspace as ks
+from synth import make_config, make_small
+from synth.configs import random_traces
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def test_tiny_fp64_config_matches_oracle():
+    # 64^3, 0.5 mm, PML 10, 160 FP64 steps, one source, 32 receivers, 8 mm sphere
+    from paper_2102_00755_amd.fwi import Handle
+    prob = make_config("tiny")
+    print("tiny config", flush=True)
+    sch = ks.scheme_for(prob)
+    S = prob.src_signals()
+    w = np.ones(prob.n_src, dtype=np.int8)
+    obs = ks.forward(sch, prob.c_true, prob.src_ijk, S, w, prob.rec_ijk, prob.nt)["traces"]
+    D, G, tr_eval = ks.tr_gradient(sch, prob.c_eval, prob.src_ijk, S, w, prob.rec_ijk, obs, prob.gamma,
+                                   prob.boundary, prob.nt)
+    h = Handle.from_problem(prob, precision=8)
+    got_obs = h.forward(torch.from_numpy(prob.c_true), torch.from_numpy(S), torch.from_numpy(w))[0].cpu().numpy()
+    assert rel(got_obs, obs) < 1e-10
+    mis, grad = h.gradient(torch.from_numpy(prob.c_eval), torch.from_numpy(S), torch.from_numpy(w),
+                           torch.from_numpy(obs))
+    g = prob.gamma.astype(bool)
+    assert abs(float(mis[0]) - D) <= 1e-10 * D
+    assert rel(grad[0].cpu().numpy()[g], G[g]) < 1e-9
+    h.close()
+
+
+@pytest.mark.parametrize("precision", [4, 8])
+def test_graph_replay_equals_eager(precision):
+    from paper_2102_00755_amd.fwi import Handle
+    prob = make_small(shape=(24, 40, 48), nt=40, n_src=2, n_rec=12, layer=2, precision=precision)
+    h = Handle.from_problem(prob, batch=2, precision=precision)
+    S = torch.from_numpy(np.stack([prob.src_signals()] * 2))
+    w = torch.from_numpy(np.stack([oracle.rademacher(5, 2), oracle.rademacher(6, 2)]))
+    c = torch.from_numpy(np.stack([prob.c_eval, prob.c_true]))
+    obs = torch.from_numpy(np.stack([random_traces(prob.nt, prob.n_rec, 1, 1e-3),
+                                     random_traces(prob.nt, prob.n_rec, 2, 1e-3)]))
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        h.use_graph = False
+        tr_e = h.forward(c, S, w).clone()
+        m_e, g_e = h.gradient(c, S, w, obs)
+        m_e, g_e = m_e.clone(), g_e.clone()
+        for rep in range(3):
+            h.use_graph = True
+            tr_g = h.forward(c, S, w)
+            m_g, g_g = h.gradient(c, S, w, obs)
+            side.synchronize()
+            assert torch.equal(tr_g, tr_e), rep
+            assert torch.equal(g_g, g_e), rep
+            assert torch.equal(m_g, m_e), rep
+            h.use_graph = False            # eager work between the replays
+            h.forward(c, S, w)
+            side.synchronize()
+    h.close()
+
+
+def test_autograd_backward_is_tr_gradient_and_matches_finite_differences():
+    from paper_2102_00755_amd.autograd import simulate
+    from paper_2102_00755_amd.fwi import Handle
+    prob = make_small(shape=(32, 32, 32), pml=4, nt=150, n_src=2, n_rec=12, layer=4, precision=8)
+    sch = ks.scheme_for(prob)
+    S = prob.src_signals()
+    w = np.array([1, -1], dtype=np.int8)
+    r = random_traces(prob.nt, prob.n_rec, seed=17, scale=1.0)
+    h = Handle.from_problem(prob, precision=8)
+    c = torch.from_numpy(prob.c_eval).cuda().requires_grad_(True)
+    St, wt, rt = torch.from_numpy(S).cuda(), torch.from_numpy(w).cuda(), torch.from_numpy(r).cuda()
+    traces = simulate(h, c, St, wt)
+    loss = (traces * rt).sum()
+    loss.backward()
+    got = c.grad.detach().cpu().numpy()
+    # parity with the oracle's TR gradient of the same linear functional
+    _, G_tr, _ = ks.tr_gradient(sch, prob.c_eval, prob.src_ijk, S, w, prob.rec_ijk, None, prob.gamma,
+                                prob.boundary, prob.nt, residual=r)
+    _, G_ex, _ = ks.exact_adjoint_gradient(sch, prob.c_eval, prob.src_ijk, S, w, prob.rec_ijk, None, prob.nt,
+                                           residual=r)
+    g = prob.gamma.astype(bool)
+    assert rel(got[g], G_tr[g]) < 1e-9
+    assert np.all(got[~g] == 0)
+    # central finite differences of the same functional at 64 seeded voxels of Gamma
+    vox = np.argwhere(prob.gamma)
+    pick = vox[np.random.default_rng(3).choice(len(vox), size=64, replace=False)]
+    hstep = 1e-2
+    fd = np.empty(64)
+    with torch.no_grad():
+        for i, (iz, iy, ix) in enumerate(pick):
+            cp = prob.c_eval.copy()
+            cm = prob.c_eval.copy()
+            cp[iz, iy, ix] += hstep
+            cm[iz, iy, ix] -= hstep
+            lp = float((h.forward(torch.from_numpy(cp), St, wt)[0] * rt).sum())
+            lm = float((h.forward(torch.from_numpy(cm), St, wt)[0] * rt).sum())
+            fd[i] = (lp - lm) / (2 * hstep)
+    at = got[tuple(pick.T)]
+    ex = G_ex[tuple(pick.T)]
+    tr = G_tr[tuple(pick.T)]
+    # FD is the exact discrete derivative; the backward differs from it only
+    # by the time-reversal approximation measured on the oracle
+    assert rel(fd, ex) < 1e-5
+    assert rel(at, fd) <= 1.05 * rel(tr, ex) + 1e-6
+    assert rel(at, fd) < 0.25
+    h.close()
+
+
+def test_serving_mix_equals_alone():
+    from paper_2102_00755_amd import fwi
+    from paper_2102_00755_amd.serving import Level, Server
+    pa = make_small(shape=(24, 40, 48), nt=30, n_src=2, n_rec=12, layer=2, precision=4, seed=31)
+    pb = make_small(shape=(16, 24, 32), nt=24, n_src=2, n_rec=12, layer=2, precision=4, seed=32)
+    levels = [Level("a", fwi.problem_kwargs(pa)), Level("b", fwi.problem_kwargs(pb))]
+    probs = {"a": pa, "b": pb}
+    rng = np.random.default_rng(0)
+    reqs = []
+    for i in range(10):
+        lv = "a" if i % 3 else "b"
+        p = probs[lv]
+        kind = "gradient" if i % 2 else "forward"
+        c = p.c_eval + rng.uniform(-5, 5, size=p.shape) * p.gamma
+        w = oracle.rademacher(100 + i, p.n_src)
+        obs = random_traces(p.nt, p.n_rec, seed=200 + i, scale=1e-3)
+        reqs.append((kind, lv, torch.from_numpy(c), torch.from_numpy(p.src_signals()), torch.from_numpy(w),
+                     torch.from_numpy(obs)))
+    budget = 3 * max(fwi.workspace_bytes(**dict(lv.kwargs), batch=1) for lv in levels)
+    srv = Server(levels, budget_bytes=budget, max_inflight=3)
+    futs = [srv.submit(k, lv, c, s, w, obs if k == "gradient" else None) for (k, lv, c, s, w, obs) in reqs]
+    mixed = [f.result(timeout=120) for f in futs]
+    st = srv.stats()
+    srv.close()
+    assert st["requests"] == len(reqs) and st["p99_ms"] >= st["p50_ms"] > 0
+    for (k, lv, c, s, w, obs), out in zip(reqs, mixed):
+        h = fwi.Handle.from_problem(probs[lv], precision=4)
+        if k == "forward":
+            alone = h.forward(c, s, w)
+            assert torch.equal(alone.cpu(), out.cpu())
+        else:
+            m, g = h.gradient(c, s, w, obs)
+            assert torch.equal(g.cpu(), out[1].cpu()) and torch.equal(m.cpu(), out[0].cpu())
+        h.close()
