@@ -115,6 +115,15 @@ int64_t fwi_workspace_bytes(const fwi_params* params, const fwi_geometry* geom);
  * Flood 2014) seeded with `seed` is 0, else -1.  Host array, n >= 0. */
 int fwi_rademacher(uint64_t seed, int32_t n, int8_t* w_out);
 
+/* Delays of delayed source encoding (Sec. 3.2, eq. DelaySE): source i fires
+ * d_i tau later, d_i ~ U[0,1).  d_i is the i-th uniform of the same SplitMix64
+ * stream as fwi_rademacher, taken at counter n + i (so weights and delays of
+ * one seed are independent): d_i = (z >> 11) * 2^-53 with z its output, and
+ * out[i] = floor(d_i * tau_steps + 1/2) whole time steps.  The caller shifts
+ * each source signal (and each source's observed data) by out[i] steps and
+ * runs nt + tau_steps steps.  Host arrays, n >= 0, tau_steps >= 0. */
+int fwi_delays(uint64_t seed, int32_t n, int32_t tau_steps, int32_t* out);
+
 /* Forward simulation (Alg. 1 forward iteration) of B problems:
  *   c        [B][nz][ny][nx]  sound speed, in [c_min, c_max]
  *   src_sig  [B][nt][n_src]   source signals s_i(t_n)

@@ -26,6 +26,7 @@ from .kspace import (  # noqa: F401
     Scheme,
     State,
     rademacher,
+    delays,
     splitmix64,
     forward,
     tr_gradient,

@@ -75,6 +75,17 @@ def rademacher(seed: int, n: int) -> np.ndarray:
     return w
 
 
+def delays(seed: int, n: int, tau_steps: int) -> np.ndarray:
+    """Delayed source encoding (Sec. 3.2, eq. DelaySE): d_i ~ U[0,1) is the
+    uniform (top 53 bits / 2^53) of SplitMix64 output n + i of ``seed``;
+    the delay in whole steps is floor(d_i tau_steps + 1/2)."""
+    out = np.empty(n, dtype=np.int32)
+    for i in range(n):
+        d = (splitmix64(seed, n + i) >> 11) / float(1 << 53)
+        out[i] = int(np.floor(d * tau_steps + 0.5))
+    return out
+
+
 # --------------------------------------------------------------------------
 # discretisation (App. B)
 # --------------------------------------------------------------------------

@@ -31,7 +31,7 @@ SUPPORTED_LENGTHS = (8, 12, 16, 24, 32, 40, 48, 56, 64, 80, 96, 112, 128, 160, 2
 
 # every symbol declared in include/fwi.h
 EXPORTED = (
-    "fwi_create", "fwi_destroy", "fwi_workspace_bytes", "fwi_rademacher", "fwi_forward",
+    "fwi_create", "fwi_destroy", "fwi_workspace_bytes", "fwi_rademacher", "fwi_delays", "fwi_forward",
     "fwi_gradient", "fwi_backward", "fwi_derivative", "fwi_timing_enable", "fwi_timing_read",
     "fwi_status_string", "fwi_last_error",
 )
@@ -85,6 +85,8 @@ def load(path: str = LIB_PATH):
     lib.fwi_workspace_bytes.restype = c_int64
     lib.fwi_rademacher.argtypes = [c_uint64, c_int32, POINTER(c_int8)]
     lib.fwi_rademacher.restype = c_int
+    lib.fwi_delays.argtypes = [c_uint64, c_int32, c_int32, POINTER(c_int32)]
+    lib.fwi_delays.restype = c_int
     lib.fwi_forward.argtypes = [h, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]
     lib.fwi_forward.restype = c_int
     lib.fwi_gradient.argtypes = [h, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,

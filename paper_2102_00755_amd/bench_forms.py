@@ -1,0 +1,180 @@
+"""Throughput and latency of the batched and served forms.
+
+    python -m paper_2102_00755_amd.bench_forms batched [--batch 16] [--nt 600]
+    python -m paper_2102_00755_amd.bench_forms serve [--requests 60] [--seconds-scale 1]
+
+batched : 16 independent Rademacher-encoded TR gradients on 128^3 (phantom
+          seeds 300..315, encoding seeds 1300..1315), run (a) one after
+          another on a batch-1 handle and (b) in one batch-16 handle whose
+          passes cover all problems per launch, with the time step captured in
+          a hipGraph; reports Mcell-steps/s and per-solve latency of both.
+serve   : Poisson-arriving forward / gradient requests (50/50) over the grid
+          levels 96^3 @ 1.0 mm (300 steps), 160^3 @ 0.75 mm (600) and
+          224x224x112 @ 0.5 mm (1200), admitted by HBM footprint; the arrival
+          rate is set to ~80 % of the measured single-stream capacity;
+          reports p50/p99 latency and Mcell-steps/s against the same requests
+          solved one at a time.
+Prints one JSON line per run.  Inputs are synthetic (synth/).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import time
+
+import numpy as np
+import torch
+
+from . import fwi
+from .serving import Level, Server
+
+
+def _gradient_inputs(prob, dev, dtype):
+    w = torch.from_numpy(fwi.rademacher(prob.enc_seed, prob.n_src))
+    S = torch.from_numpy(prob.src_signals()).to(dtype)
+    return (torch.from_numpy(prob.c_eval).to(dtype), torch.from_numpy(prob.c_true).to(dtype), S, w)
+
+
+def batched(args) -> dict:
+    from synth import make_config
+    B = args.batch
+    probs = [make_config("batch", index=i, nt=args.nt) for i in range(B)]
+    base = probs[0]
+    # one geometry for the batch: all emitters of the bowl, per-problem weights
+    # select each problem's encoded subset (zero for the others)
+    emitters = base.meta["all_emitters"]
+    n_all = emitters.shape[0]
+    kw = fwi.problem_kwargs(base)
+    kw["src_ijk"] = emitters
+    dev = torch.device("cuda", 0)
+    dtype = torch.float32
+    c_eval = torch.stack([torch.from_numpy(p.c_eval) for p in probs]).to(dev, dtype)
+    c_true = torch.stack([torch.from_numpy(p.c_true) for p in probs]).to(dev, dtype)
+    W = torch.zeros((B, n_all), dtype=torch.int8)
+    for i, p in enumerate(probs):
+        W[i, p.meta["emitter_index"]] = torch.from_numpy(fwi.rademacher(p.enc_seed, p.n_src))
+    W = W.to(dev)
+    S = torch.from_numpy(np.repeat(base.pulse[:, None], n_all, axis=1)).to(dev, dtype)
+    S = S.unsqueeze(0).expand(B, -1, -1).contiguous()
+    side = torch.cuda.Stream(device=dev)
+    out = {}
+    with torch.cuda.stream(side):
+        hb = fwi.Handle(**kw, batch=B)
+        hb.use_graph = True
+        obs = hb.forward(c_true, S, W)
+        side.synchronize()
+        hb.gradient(c_eval, S, W, obs)        # warm-up
+        side.synchronize()
+        t0 = time.perf_counter()
+        mis_b, g_b = hb.gradient(c_eval, S, W, obs)
+        side.synchronize()
+        t_b = time.perf_counter() - t0
+        h1 = fwi.Handle(**kw, batch=1)
+        h1.use_graph = True
+        h1.gradient(c_eval[0], S[0], W[0], obs[0])
+        side.synchronize()
+        lat = []
+        t0 = time.perf_counter()
+        for i in range(B):
+            t1 = time.perf_counter()
+            m1, g1 = h1.gradient(c_eval[i], S[i], W[i], obs[i])
+            side.synchronize()
+            lat.append(time.perf_counter() - t1)
+            if i == 0:
+                same = bool(torch.equal(g1[0], g_b[0]))
+        t_s = time.perf_counter() - t0
+        hb.close()
+        h1.close()
+    work = 3.0 * base.n_cells * base.nt * B
+    out.update({
+        "form": "batched", "batch": B, "grid": list(base.shape[::-1]), "nt": base.nt,
+        "batched_Mcell_steps_per_s": work / t_b / 1e6, "batched_wall_s": t_b,
+        "single_Mcell_steps_per_s": work / t_s / 1e6, "single_wall_s": t_s,
+        "single_p50_ms": float(np.percentile(np.array(lat) * 1e3, 50)),
+        "single_p99_ms": float(np.percentile(np.array(lat) * 1e3, 99)),
+        "batched_equals_single": same, "hipgraph": True,
+    })
+    return out
+
+
+def serve(args) -> dict:
+    from synth import make_config
+    names = ["serve96", "serve160", "serve224"]
+    probs = {n: make_config(n) for n in names}
+    levels = [Level(n, fwi.problem_kwargs(p)) for n, p in probs.items()]
+    rng = np.random.default_rng(4)
+    reqs = []
+    for i in range(args.requests):
+        lv = names[int(rng.integers(0, 3))]
+        kind = "gradient" if rng.random() < 0.5 else "forward"
+        p = probs[lv]
+        c = p.c_eval + rng.uniform(-5, 5, size=p.shape) * p.gamma
+        w = torch.from_numpy(fwi.rademacher(p.enc_seed + i, p.n_src))
+        reqs.append((kind, lv, torch.from_numpy(c), torch.from_numpy(p.src_signals()), w))
+    # observed data per level (synthetic: forward at c_true, computed up front)
+    obs = {}
+    for n, p in probs.items():
+        h = fwi.Handle.from_problem(p)
+        obs[n] = h.forward(torch.from_numpy(p.c_true), torch.from_numpy(p.src_signals()),
+                           torch.from_numpy(fwi.rademacher(p.enc_seed, p.n_src)))[0].cpu()
+        h.close()
+    # single-stream capacity: every request alone, one after another
+    solo_lat = []
+    hs = {n: fwi.Handle.from_problem(p) for n, p in probs.items()}
+    for n in names:   # warm-up
+        hs[n].forward(torch.from_numpy(probs[n].c_eval), torch.from_numpy(probs[n].src_signals()),
+                      torch.from_numpy(fwi.rademacher(1, probs[n].n_src)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for kind, lv, c, s, w in reqs:
+        t1 = time.perf_counter()
+        if kind == "forward":
+            hs[lv].forward(c, s, w)
+        else:
+            hs[lv].gradient(c, s, w, obs[lv])
+        torch.cuda.synchronize()
+        solo_lat.append(time.perf_counter() - t1)
+    t_solo = time.perf_counter() - t0
+    for h in hs.values():
+        h.close()
+    work = sum(probs[lv].n_cells * probs[lv].nt * (3 if k == "gradient" else 1) for k, lv, *_ in reqs)
+    rate = 0.8 * len(reqs) / t_solo                # arrivals per second
+    gaps = rng.exponential(1.0 / rate, size=len(reqs))
+    budget = int(args.budget_gb * 2 ** 30)
+    srv = Server(levels, budget_bytes=budget, max_inflight=args.inflight)
+    futs = []
+    t_start = time.perf_counter()
+    for (kind, lv, c, s, w), gap in zip(reqs, gaps):
+        time.sleep(gap)
+        futs.append(srv.submit(kind, lv, c, s, w, obs[lv] if kind == "gradient" else None))
+    for f in futs:
+        f.result()
+    st = srv.stats()
+    srv.close()
+    return {
+        "form": "serve", "requests": len(reqs), "levels": names, "arrival_rate_per_s": rate,
+        "served_Mcell_steps_per_s": st["Mcell-steps/s"], "served_p50_ms": st["p50_ms"],
+        "served_p99_ms": st["p99_ms"], "solo_Mcell_steps_per_s": work / t_solo / 1e6,
+        "solo_p50_ms": float(np.percentile(np.array(solo_lat) * 1e3, 50)),
+        "solo_p99_ms": float(np.percentile(np.array(solo_lat) * 1e3, 99)),
+        "inflight": args.inflight, "handles": st["handles"], "device_bytes": st["device_bytes"],
+        "wall_s": time.perf_counter() - t_start,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("form", choices=["batched", "serve"])
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--nt", type=int, default=None)
+    ap.add_argument("--requests", type=int, default=60)
+    ap.add_argument("--inflight", type=int, default=4)
+    ap.add_argument("--budget-gb", type=float, default=64.0)
+    args = ap.parse_args()
+    res = batched(args) if args.form == "batched" else serve(args)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

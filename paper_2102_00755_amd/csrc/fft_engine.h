@@ -182,7 +182,29 @@ template <bool INV, typename C> struct Bfly<3, INV, C> : BflyOdd<3, INV, C> {};
 template <bool INV, typename C> struct Bfly<5, INV, C> : BflyOdd<5, INV, C> {};
 template <bool INV, typename C> struct Bfly<7, INV, C> : BflyOdd<7, INV, C> {};
 
-// One Stockham stage and the recursion over the plan.
+// Thread mapping of one stage.  Work items are (c, jj, k): column c < TW,
+// position jj < NS inside the current sub-transforms, sub-transform k < K
+// (K = L / (NS R)); butterfly j = k NS + jj.  Threads are laid out c fastest,
+// then jj, then k, so LDS reads of a stage are contiguous, and each thread's
+// items differ by compile-time strides: every address is a per-thread base
+// plus a constant, and when TW NS <= NT a thread keeps one jj for all its
+// items, so its twiddles are loaded once per stage.
+constexpr int largest_divisor_le(int n, int cap) {
+  int best = 1;
+  for (int d = 1; d <= n && d <= cap; ++d)
+    if (n % d == 0) best = d;
+  return best;
+}
+
+template <int TW, int NS, int K, int NT> struct StageMap {
+  static constexpr bool A = TW * NS <= NT;                       // one jj per thread
+  static constexpr int KB = A ? largest_divisor_le(K, NT / (TW * NS)) : 1;
+  static constexpr int JB = A ? NS : largest_divisor_le(NS, NT / TW);
+  static constexpr int TU = A ? TW * NS * KB : TW * JB;          // threads with work
+  static constexpr int NJ = A ? 1 : NS / JB;                     // jj values per thread
+  static constexpr int NK = A ? K / KB : K;                      // k values per thread
+};
+
 template <typename T, int L, int TW, int TWP, int NT, bool INV, int S>
 struct Stage {
   static __device__ __forceinline__ void run(cplx<T>* buf, const cplx<T>* __restrict__ tw) {
@@ -192,42 +214,53 @@ struct Stage {
       constexpr int R = P.r[S];
       constexpr int NS = plan_prefix(L, S);
       constexpr int LR = L / R;
-      constexpr int NB = LR * TW;
-      constexpr int PER = (NB + NT - 1) / NT;
+      constexpr int K = L / (NS * R);
       constexpr int TSTEP = L / (NS * R);
+      using Map = StageMap<TW, NS, K, NT>;
       const int tid = threadIdx.x;
-      C v[PER][R];
+      const bool active = tid < Map::TU;
+      const int c = tid % TW;
+      const int jq = tid / TW;                                   // jj (+ NS kb) or jb
+      const int jj0 = Map::A ? (jq % NS) : jq;
+      const int kb = Map::A ? (jq / NS) : 0;
+      C v[Map::NJ][Map::NK][R];
+      if (active) {
 #pragma unroll
-      for (int i = 0; i < PER; ++i) {
-        const int q = i * NT + tid;
-        if (NB % NT == 0 || q < NB) {
-          const int c = q % TW;
-          const int j = q / TW;
-          const int jj = j % NS;
+        for (int a = 0; a < Map::NJ; ++a) {
+          const int jj = jj0 + a * Map::JB;
+          C w[R];
+          if (NS > 1) {
 #pragma unroll
-          for (int t = 0; t < R; ++t) {
-            C x = buf[(j + t * LR) * TWP + c];
-            if (NS > 1 && t > 0) {
-              C w = tw[t * jj * TSTEP];
-              if (INV) w = cconj(w);
-              x = cmul(x, w);
+            for (int t = 1; t < R; ++t) {
+              C x = tw[t * jj * TSTEP];
+              w[t] = INV ? cconj(x) : x;
             }
-            v[i][t] = x;
+          }
+#pragma unroll
+          for (int b = 0; b < Map::NK; ++b) {
+            const int k = kb + b * Map::KB;
+            const int j = k * NS + jj;
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+              C x = buf[(j + t * LR) * TWP + c];
+              if (NS > 1 && t > 0) x = cmul(x, w[t]);
+              v[a][b][t] = x;
+            }
           }
         }
       }
       __syncthreads();
+      if (active) {
 #pragma unroll
-      for (int i = 0; i < PER; ++i) {
-        const int q = i * NT + tid;
-        if (NB % NT == 0 || q < NB) {
-          const int c = q % TW;
-          const int j = q / TW;
-          const int jj = j % NS;
-          const int k = j / NS;
-          Bfly<R, INV, C>::run(v[i]);
+        for (int a = 0; a < Map::NJ; ++a) {
+          const int jj = jj0 + a * Map::JB;
 #pragma unroll
-          for (int u = 0; u < R; ++u) buf[(k * NS * R + jj + u * NS) * TWP + c] = v[i][u];
+          for (int b = 0; b < Map::NK; ++b) {
+            const int k = kb + b * Map::KB;
+            Bfly<R, INV, C>::run(v[a][b]);
+#pragma unroll
+            for (int u = 0; u < R; ++u) buf[(k * NS * R + jj + u * NS) * TWP + c] = v[a][b][u];
+          }
         }
       }
       __syncthreads();

@@ -508,7 +508,8 @@ template <typename T> struct Engine : EngineBase {
   double sbytes() const { return (double)(d.M + 1) * d.ny * d.nz * sizeof(C); }
   double fbytes() const { return (double)d.nfield * sizeof(T); }
 
-  int step_spectral(int slot0, int na, int slot1, int nslots, hipStream_t st) {
+  // Y3 .. Y2 of one step; half_only stops after the velocity pass X1
+  int step_spectral(int slot0, int na, int slot1, int nslots, hipStream_t st, bool half_only = false) {
     const dim3 gy(ntx() * d.nz, nslots * 1), gy3(ntx() * d.nz, nslots * 3);
     const dim3 gz(ntx() * d.ny, nslots), gz3(ntx() * d.ny, nslots * 3);
     const double S = sbytes(), F = fbytes(), ns = nslots;
@@ -529,6 +530,7 @@ template <typename T> struct Engine : EngineBase {
     ev = timer.begin(st);
     FWI_HIP(launch_x_vel<T>(d.M, dim3((d.nlines + lpb - 1) / lpb, nslots), st, xa));       // X1
     timer.end(ev, FWI_PASS_X_VEL, ns * (6 * S + 6 * F), st);
+    if (half_only) return FWI_OK;
     ev = timer.begin(st);
     FWI_HIP(launch_axis_y<T>(d.ny, false, gy3, st, axis_args(slot0, na, slot1, 3, 0)));      // Y1
     timer.end(ev, FWI_PASS_Y_FWD, 6 * ns * S, st);
@@ -688,14 +690,24 @@ template <typename T> struct Engine : EngineBase {
     a.adj_src = adj; a.tape = tape;
     // TR initial state: zero interior (or the final forward state), dGamma <- g^{N-1}
     if (final_state) {
-      // v <- -v^{N+1/2}: one more velocity half step of the forward, negated
-      return fail(FWI_ERR_INVALID_ARG, "FWI_TR_FINAL_STATE is not available in this build");
+      // the forward slots still hold v^{N-1/2}, rho^N and the x-spectrum of
+      // p^N: one more velocity update gives v^{N+1/2}; the TR starts from
+      // (rho^N, -v^{N+1/2}) so that its first velocity update returns -v^{N-1/2}
+      if ((rc = step_spectral(tr0, B, tr0, B, st, true))) return rc;
+      for (int b = 0; b < B; ++b) {
+        hipLaunchKernelGGL((k_scale<T>), dim3(4096), dim3(256), 0, st, slots_host[tr0 + b].v[0],
+                           (long long)3 * d.nfield, (T)-1);
+        FWI_HIP(hipGetLastError());
+      }
+      a.tr_state_mode = 2;
+    } else {
+      for (int b = 0; b < B; ++b)
+        if ((rc = zero_velocity(tr0 + b, st))) return rc;
+      a.tr_state_mode = 1;
     }
-    for (int b = 0; b < B; ++b)
-      if ((rc = zero_velocity(tr0 + b, st))) return rc;
-    a.tape_row = N - 1; a.tr_zero_state = 1; a.ring_c = 0; a.step = 0;
+    a.tape_row = N - 1; a.ring_c = 0; a.step = 0;
     if ((rc = launch_x2(XM_TRONLY, B, a, st))) return rc;
-    a.tr_zero_state = 0;
+    a.tr_state_mode = 0;
     if (N == 1) {  // p_tr^(1) = 0
       if ((rc = fill<T>(ring, (long long)B * 3 * d.n_gam, (T)0, st))) return rc;
     }
@@ -884,6 +896,19 @@ int fwi_rademacher(uint64_t seed, int32_t n, int8_t* w_out) {
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
     z = z ^ (z >> 31);
     w_out[i] = (z >> 63) ? (int8_t)-1 : (int8_t)1;
+  }
+  return FWI_OK;
+}
+
+int fwi_delays(uint64_t seed, int32_t n, int32_t tau_steps, int32_t* out) {
+  if (n < 0 || tau_steps < 0 || (n > 0 && !out)) return fail(FWI_ERR_INVALID_ARG, "bad arguments");
+  for (int32_t i = 0; i < n; ++i) {
+    uint64_t z = seed + (uint64_t)(n + i + 1) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z = z ^ (z >> 31);
+    const double d = (double)(z >> 11) * (1.0 / 9007199254740992.0);
+    out[i] = (int32_t)std::floor(d * tau_steps + 0.5);
   }
   return FWI_OK;
 }

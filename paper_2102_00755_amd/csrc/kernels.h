@@ -123,6 +123,152 @@ __device__ __forceinline__ void tile_store(const cplx<T>* buf, cplx<T>* g, size_
   }
 }
 
+// ---- persistent axis passes -------------------------------------------------
+// Each workgroup walks the tile list with stride gridDim.x.  The global loads
+// of the next tile are issued into registers right after the current tile has
+// been written to LDS, so they are in flight during the current tile's FFTs
+// and stores (one tile of prefetch per workgroup).
+template <typename T> struct TileRef {
+  cplx<T>* g;   // first element of the tile in its field
+  int ncol;     // valid columns (ragged last tile)
+  int kx0;      // first kx column
+  int outer;    // z (y pass) or y (z pass)
+  int s, f;     // slot and field
+};
+
+template <typename T, int TW>
+__device__ __forceinline__ TileRef<T> tile_ref(const AxisArgs<T>& a, int item, int nouter, int nf_tile,
+                                               size_t outer_stride) {
+  const int ntx = (a.d.M + TW) / TW;
+  const int per = ntx * nouter;
+  const int si = item / per;
+  const int rem = item % per;
+  const int outer = rem / ntx, tile = rem % ntx;
+  TileRef<T> t;
+  t.s = slot_of(si / nf_tile, a.slot0, a.na, a.slot1);
+  t.f = a.f0 + si % nf_tile;
+  t.kx0 = tile * TW;
+  t.g = a.slots[t.s].spec[t.f] + (size_t)outer * outer_stride + (size_t)t.kx0;
+  t.ncol = min(TW, a.d.M + 1 - t.kx0);
+  t.outer = outer;
+  return t;
+}
+
+template <typename T, int L, int TW, int NT>
+__device__ __forceinline__ void tile_prefetch(cplx<T>* pre, const cplx<T>* g, int ncol, size_t rstride) {
+  using C = cplx<T>;
+  constexpr int E = L * TW;
+  constexpr int EPT = (E + NT - 1) / NT;
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = (int)threadIdx.x + i * NT;
+    const int r = e / TW, c = e % TW;
+    pre[i] = (c < ncol && (E % NT == 0 || e < E)) ? g[(size_t)r * rstride + c] : cmake<C>((T)0, (T)0);
+  }
+}
+template <typename T, int L, int TW, int NT>
+__device__ __forceinline__ void tile_commit(cplx<T>* buf, const cplx<T>* pre) {
+  constexpr int E = L * TW;
+  constexpr int EPT = (E + NT - 1) / NT;
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = (int)threadIdx.x + i * NT;
+    if (E % NT == 0 || e < E) buf[e] = pre[i];
+  }
+}
+
+// kappa * scale * i k_f exp(sign i k_f dx / 2) at row r (kz), column kx, y
+template <typename T>
+__device__ __forceinline__ cplx<T> zmult(const AxisArgs<T>& a, const cplx<T>* const* sfac, int f, int kx, int y,
+                                         int r, T ky2) {
+  const T u = a.kap_a * (a.tb.ksq[0][kx] + ky2 + a.tb.ksq[2][r]);
+  const T kap = sinc_u(u) * a.scale;
+  const cplx<T> sf = (f == 0) ? sfac[0][kx] : ((f == 1) ? sfac[1][y] : sfac[2][r]);
+  return cscale(sf, kap);
+}
+
+enum AxisKind { AK_Y = 0, AK_ZMINUS = 1, AK_ZPLUS = 2 };
+
+// Persistent axis pass over nitems tiles:
+//   AK_Y      in-place FFT along y (forward or inverse by INV) of nf fields
+//   AK_ZMINUS field f -> F_z^-1 m-_f F_z field f                (Z1)
+//   AK_ZPLUS  field 0 -> fields 0,1,2 = F_z^-1 m+_a F_z field 0  (Z2)
+template <typename T, int L, int KIND, bool INV>
+__global__ void __launch_bounds__(axis_nt(L, axis_tw<T>()))
+k_axis_persist(AxisArgs<T> a, int nitems) {
+  using C = cplx<T>;
+  constexpr int TW = axis_tw<T>();
+  constexpr int NT = axis_nt(L, TW);
+  constexpr int E = L * TW;
+  constexpr int EPT = (E + NT - 1) / NT;
+  __shared__ C buf[L * TW];
+  const size_t px = a.d.px;
+  const int nouter = (KIND == AK_Y) ? a.d.nz : a.d.ny;
+  const size_t ostride = (KIND == AK_Y) ? (size_t)a.d.ny * px : px;
+  const size_t rstride = (KIND == AK_Y) ? px : (size_t)a.d.ny * px;
+  const int nf_tile = (KIND == AK_ZPLUS) ? 1 : a.nf;
+  C pre[EPT];
+  int item = blockIdx.x;
+  if (item < nitems) {
+    const TileRef<T> t = tile_ref<T, TW>(a, item, nouter, nf_tile, ostride);
+    tile_prefetch<T, L, TW, NT>(pre, t.g, t.ncol, rstride);
+  }
+  for (; item < nitems; item += gridDim.x) {
+    const TileRef<T> t = tile_ref<T, TW>(a, item, nouter, nf_tile, ostride);
+    tile_commit<T, L, TW, NT>(buf, pre);
+    __syncthreads();
+    const int next = item + gridDim.x;
+    if (next < nitems) {
+      const TileRef<T> tn = tile_ref<T, TW>(a, next, nouter, nf_tile, ostride);
+      tile_prefetch<T, L, TW, NT>(pre, tn.g, tn.ncol, rstride);
+    }
+    if (KIND == AK_Y) {
+      lds_fft<T, L, TW, TW, NT, INV>(buf, a.tb.tw_y);
+      tile_store<T, L, TW, NT>(buf, t.g, rstride, t.ncol);
+    } else if (KIND == AK_ZMINUS) {
+      lds_fft<T, L, TW, TW, NT, false>(buf, a.tb.tw_z);
+      const T ky2 = a.tb.ksq[1][t.outer];
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int e = (int)threadIdx.x + i * NT;
+        const int r = e / TW, c = e % TW;
+        if ((E % NT == 0 || e < E) && c < t.ncol)
+          buf[e] = cmul(zmult<T>(a, a.tb.sfac_m, t.f, t.kx0 + c, t.outer, r, ky2), buf[e]);
+      }
+      __syncthreads();
+      lds_fft<T, L, TW, TW, NT, true>(buf, a.tb.tw_z);
+      tile_store<T, L, TW, NT>(buf, t.g, rstride, t.ncol);
+    } else {
+      lds_fft<T, L, TW, TW, NT, false>(buf, a.tb.tw_z);
+      const T ky2 = a.tb.ksq[1][t.outer];
+      C xr[EPT];
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int e = (int)threadIdx.x + i * NT;
+        if (E % NT == 0 || e < E) xr[i] = buf[e];
+      }
+      const size_t off = (size_t)(t.g - a.slots[t.s].spec[0]);
+#pragma unroll
+      for (int f = 0; f < 3; ++f) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+          const int e = (int)threadIdx.x + i * NT;
+          const int r = e / TW, c = e % TW;
+          if (E % NT == 0 || e < E) {
+            const int kx = min(t.kx0 + c, a.d.M);
+            buf[e] = cmul(zmult<T>(a, a.tb.sfac_p, f, kx, t.outer, r, ky2), xr[i]);
+          }
+        }
+        __syncthreads();
+        lds_fft<T, L, TW, TW, NT, true>(buf, a.tb.tw_z);
+        tile_store<T, L, TW, NT>(buf, a.slots[t.s].spec[f] + off, rstride, t.ncol);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Y pass: in-place FFT along y of nf fields per slot.  L == ny.
 template <typename T, int L, bool INV>
 __global__ void __launch_bounds__(axis_nt(L, axis_tw<T>()))
@@ -243,47 +389,73 @@ k_axis_z_plus(AxisArgs<T> a) {
 // ----------------------------------------------------------------------------
 // x passes: LPB consecutive x-lines per workgroup, real <-> half spectrum
 // ----------------------------------------------------------------------------
-// Load NREG spectra lines (M+1 complex each) of LPB lines into columns
-// [col0, col0 + NREG*LPB) of buf (rows 0..M).
+// 2D lane layout of the x passes: KT lanes (a power of two >= NK, at most
+// the block) run along the fast index k of a line, RT = X_NT / KT rows of
+// lanes along the slow index r (line, region or column).  Thread t owns
+// k = t % KT + KT ik and r = t / KT + RT ir: every address is a per-thread
+// base plus a compile-time offset, and consecutive lanes touch consecutive k.
+constexpr int pow2_at_least(int n) {
+  int p = 64;
+  while (p < n && p < X_NT) p *= 2;
+  return p;
+}
+template <int NR, int NK> struct Lanes {
+  static constexpr int KT = pow2_at_least(NK);
+  static constexpr int RT = X_NT / KT;
+  static constexpr int KI = (NK + KT - 1) / KT;
+  static constexpr int RI = (NR + RT - 1) / RT;
+  static constexpr int NI = RI * KI;   // items per thread
+};
+template <int NR, int NK, typename F>
+__device__ __forceinline__ void lanes2d(F&& fn) {
+  using Ly = Lanes<NR, NK>;
+  const int kq = (int)threadIdx.x % Ly::KT;
+  const int rq = (int)threadIdx.x / Ly::KT;
+#pragma unroll
+  for (int ir = 0; ir < Ly::RI; ++ir) {
+#pragma unroll
+    for (int ik = 0; ik < Ly::KI; ++ik) {
+      const int r = rq + ir * Ly::RT;
+      const int k = kq + ik * Ly::KT;
+      if ((NR % Ly::RT == 0 || r < NR) && (NK % Ly::KT == 0 || k < NK)) fn(ir * Ly::KI + ik, r, k);
+    }
+  }
+}
+
+// Spectra lines (M+1 complex) of NREG regions x LPB lines <-> LDS columns
+// col0 + f LPB + l, rows 0..M.
+template <typename T, int M, int LPB, int NREG>
+__device__ __forceinline__ void x_prefetch_spectra(cplx<T>* pre, cplx<T>* const* spec, int l0, int nl, size_t px) {
+  using C = cplx<T>;
+  lanes2d<NREG * LPB, M + 1>([&](int i, int r, int k) {
+    const int f = r / LPB, l = r % LPB;
+    pre[i] = (l < nl) ? spec[f][(size_t)(l0 + l) * px + k] : cmake<C>((T)0, (T)0);
+  });
+}
+template <typename T, int M, int LPB, int TWP, int NREG>
+__device__ __forceinline__ void x_commit_spectra(cplx<T>* buf, const cplx<T>* pre, int col0) {
+  lanes2d<NREG * LPB, M + 1>([&](int i, int r, int k) {
+    const int f = r / LPB, l = r % LPB;
+    buf[k * TWP + col0 + f * LPB + l] = pre[i];
+  });
+}
+template <typename T, int M, int LPB, int NREG> struct SpecRegs {
+  static constexpr int N = Lanes<NREG * LPB, M + 1>::NI;
+};
 template <typename T, int M, int LPB, int TWP, int NREG>
 __device__ __forceinline__ void x_load_spectra(cplx<T>* buf, cplx<T>* const* spec, int col0, int l0, int nl,
                                                size_t px) {
-  using C = cplx<T>;
-  constexpr int PER = (M + 1) * LPB;
-  constexpr int E = NREG * PER;
-  constexpr int EPT = (E + X_NT - 1) / X_NT;
-  C tmp[EPT];
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = (int)threadIdx.x + i * X_NT;
-    const int f = e / PER;
-    const int rem = e % PER;
-    const int l = rem / (M + 1), k = rem % (M + 1);
-    tmp[i] = (e < E && l < nl) ? spec[f][(size_t)(l0 + l) * px + k] : cmake<C>((T)0, (T)0);
-  }
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = (int)threadIdx.x + i * X_NT;
-    const int f = e / PER;
-    const int rem = e % PER;
-    const int l = rem / (M + 1), k = rem % (M + 1);
-    if (e < E) buf[k * TWP + col0 + f * LPB + l] = tmp[i];
-  }
+  cplx<T> tmp[SpecRegs<T, M, LPB, NREG>::N];
+  x_prefetch_spectra<T, M, LPB, NREG>(tmp, spec, l0, nl, px);
+  x_commit_spectra<T, M, LPB, TWP, NREG>(buf, tmp, col0);
 }
 template <typename T, int M, int LPB, int TWP, int NREG>
 __device__ __forceinline__ void x_store_spectra(const cplx<T>* buf, cplx<T>* const* spec, int col0, int l0,
                                                 int nl, size_t px) {
-  constexpr int PER = (M + 1) * LPB;
-  constexpr int E = NREG * PER;
-  constexpr int EPT = (E + X_NT - 1) / X_NT;
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = (int)threadIdx.x + i * X_NT;
-    const int f = e / PER;
-    const int rem = e % PER;
-    const int l = rem / (M + 1), k = rem % (M + 1);
-    if (e < E && l < nl) spec[f][(size_t)(l0 + l) * px + k] = buf[k * TWP + col0 + f * LPB + l];
-  }
+  lanes2d<NREG * LPB, M + 1>([&](int, int r, int k) {
+    const int f = r / LPB, l = r % LPB;
+    if (l < nl) spec[f][(size_t)(l0 + l) * px + k] = buf[k * TWP + col0 + f * LPB + l];
+  });
 }
 
 // Half spectrum X[0..M] of a length-2M real line -> Z[0..M-1] whose
@@ -294,8 +466,7 @@ __device__ __forceinline__ void x_store_spectra(const cplx<T>* buf, cplx<T>* con
 template <typename T, int M, int TWP, int NCOL>
 __device__ __forceinline__ void c2r_pre(cplx<T>* buf, const cplx<T>* __restrict__ rtw) {
   using C = cplx<T>;
-  for (int e = threadIdx.x; e < (M / 2 + 1) * NCOL; e += X_NT) {
-    const int col = e % NCOL, k = e / NCOL;
+  lanes2d<NCOL, M / 2 + 1>([&](int, int col, int k) {
     if (k == 0) {
       const C x0 = buf[col], xm = buf[M * TWP + col];
       buf[col] = cmake<C>(x0.x + xm.x, x0.x - xm.x);
@@ -311,7 +482,7 @@ __device__ __forceinline__ void c2r_pre(cplx<T>* buf, const cplx<T>* __restrict_
         buf[(M - k) * TWP + col] = cmake<C>(s2.x - t2.y, s2.y + t2.x);
       }
     }
-  }
+  });
 }
 
 // Z[0..M-1] = DFT_M(x[2n] + i x[2n+1]) -> half spectrum X[0..M] of x:
@@ -320,8 +491,7 @@ template <typename T, int M, int TWP, int NCOL>
 __device__ __forceinline__ void r2c_post(cplx<T>* buf, const cplx<T>* __restrict__ rtw) {
   using C = cplx<T>;
   const T h = (T)0.5;
-  for (int e = threadIdx.x; e < (M / 2 + 1) * NCOL; e += X_NT) {
-    const int col = e % NCOL, k = e / NCOL;
+  lanes2d<NCOL, M / 2 + 1>([&](int, int col, int k) {
     if (k == 0) {
       const C z0 = buf[col];
       buf[col] = cmake<C>(z0.x + z0.y, (T)0);
@@ -338,7 +508,7 @@ __device__ __forceinline__ void r2c_post(cplx<T>* buf, const cplx<T>* __restrict
         buf[(M - k) * TWP + col] = cmake<C>(h * (s2.x + t2.y), h * (s2.y - t2.x));
       }
     }
-  }
+  });
 }
 
 template <typename T> struct XArgs {
@@ -364,27 +534,19 @@ __global__ void __launch_bounds__(X_NT) k_x_velocity(XArgs<T> a) {
   const size_t px = a.d.px;
   const int nx = a.d.nx;
   // prefetch the velocities: in flight during the C2R transforms
-  constexpr int EB = (M * LPB + X_NT - 1) / X_NT;
-  C vv[EB][3];
-#pragma unroll
-  for (int i = 0; i < EB; ++i) {
-    const int e = (int)threadIdx.x + i * X_NT;
-    const int l = e / M, n = e % M;
-    const bool ok = (e < M * LPB) && (l < nl);
+  C vv[Lanes<LPB, M>::NI][3];
+  lanes2d<LPB, M>([&](int i, int l, int n) {
 #pragma unroll
     for (int f = 0; f < 3; ++f)
-      vv[i][f] = ok ? reinterpret_cast<const C*>(sl.v[f] + (size_t)(l0 + l) * nx)[n] : cmake<C>((T)0, (T)0);
-  }
+      vv[i][f] = (l < nl) ? reinterpret_cast<const C*>(sl.v[f] + (size_t)(l0 + l) * nx)[n] : cmake<C>((T)0, (T)0);
+  });
   x_load_spectra<T, M, LPB, TWP, 3>(buf, sl.spec, 0, l0, nl, px);
   __syncthreads();
   c2r_pre<T, M, TWP, NC>(buf, a.tb.rtw);
   __syncthreads();
   lds_fft<T, M, NC, TWP, X_NT, true>(buf, a.tb.tw_x);
-#pragma unroll
-  for (int i = 0; i < EB; ++i) {
-    const int e = (int)threadIdx.x + i * X_NT;
-    const int l = e / M, n = e % M;
-    if (e >= M * LPB || l >= nl) continue;
+  lanes2d<LPB, M>([&](int i, int l, int n) {
+    if (l >= nl) return;
     const int line = l0 + l;
     const int yy = line % a.d.ny, zz = line / a.d.ny;
 #pragma unroll
@@ -398,12 +560,90 @@ __global__ void __launch_bounds__(X_NT) k_x_velocity(XArgs<T> a) {
       reinterpret_cast<C*>(sl.v[f] + (size_t)line * nx)[n] = vn;
       buf[n * TWP + f * LPB + l] = vn;
     }
-  }
+  });
   __syncthreads();
   lds_fft<T, M, NC, TWP, X_NT, false>(buf, a.tb.tw_x);
   r2c_post<T, M, TWP, NC>(buf, a.tb.rtw);
   __syncthreads();
   x_store_spectra<T, M, LPB, TWP, 3>(buf, sl.spec, 0, l0, nl, px);
+}
+
+// Persistent X1: workgroups walk the (slot, line group) items with stride
+// gridDim.x.  The next item's spectra are loaded into registers right after
+// the current item's spectra reach LDS and its velocities right after the
+// current velocities are consumed, so HBM traffic overlaps the transforms.
+template <typename T, int M>
+__global__ void __launch_bounds__(X_NT) k_x_velocity_persist(XArgs<T> a, int nitems) {
+  using C = cplx<T>;
+  constexpr int LPB = x_lpb_vel<T>(M);
+  constexpr int NC = 3 * LPB;
+  constexpr int TWP = NC;
+  __shared__ C buf[(M + 1) * TWP];
+  const int ngroups = (a.d.nlines + LPB - 1) / LPB;
+  const size_t px = a.d.px;
+  const int nx = a.d.nx;
+  C pre[SpecRegs<T, M, LPB, 3>::N];
+  C vv[Lanes<LPB, M>::NI][3];
+  auto item_slot = [&](int it) { return a.slots[slot_of(it / ngroups, a.slot0, a.na, a.slot1)]; };
+  auto prefetch_v = [&](const Slot<T>& sl, int l0, int nl) {
+    lanes2d<LPB, M>([&](int i, int l, int n) {
+#pragma unroll
+      for (int f = 0; f < 3; ++f)
+        vv[i][f] = (l < nl) ? reinterpret_cast<const C*>(sl.v[f] + (size_t)(l0 + l) * nx)[n] : cmake<C>((T)0, (T)0);
+    });
+  };
+  int item = blockIdx.x;
+  if (item < nitems) {
+    const Slot<T> sl = item_slot(item);
+    const int l0 = (item % ngroups) * LPB;
+    const int nl = min(LPB, a.d.nlines - l0);
+    prefetch_v(sl, l0, nl);
+    x_prefetch_spectra<T, M, LPB, 3>(pre, sl.spec, l0, nl, px);
+  }
+  for (; item < nitems; item += gridDim.x) {
+    const Slot<T> sl = item_slot(item);
+    const int l0 = (item % ngroups) * LPB;
+    const int nl = min(LPB, a.d.nlines - l0);
+    const int next = item + gridDim.x;
+    const bool has_next = next < nitems;
+    x_commit_spectra<T, M, LPB, TWP, 3>(buf, pre, 0);
+    __syncthreads();
+    if (has_next) {
+      const Slot<T> sn = item_slot(next);
+      const int n0 = (next % ngroups) * LPB;
+      x_prefetch_spectra<T, M, LPB, 3>(pre, sn.spec, n0, min(LPB, a.d.nlines - n0), px);
+    }
+    c2r_pre<T, M, TWP, NC>(buf, a.tb.rtw);
+    __syncthreads();
+    lds_fft<T, M, NC, TWP, X_NT, true>(buf, a.tb.tw_x);
+    lanes2d<LPB, M>([&](int i, int l, int n) {
+      if (l >= nl) return;
+      const int line = l0 + l;
+      const int yy = line % a.d.ny, zz = line / a.d.ny;
+#pragma unroll
+      for (int f = 0; f < 3; ++f) {
+        const C dp = buf[n * TWP + f * LPB + l];
+        T lx, ly;
+        if (f == 0) { lx = a.tb.pml_s[0][2 * n]; ly = a.tb.pml_s[0][2 * n + 1]; }
+        else if (f == 1) { lx = ly = a.tb.pml_s[1][yy]; }
+        else { lx = ly = a.tb.pml_s[2][zz]; }
+        const C vn = cmake<C>(lx * (lx * vv[i][f].x - a.dt_rho * dp.x), ly * (ly * vv[i][f].y - a.dt_rho * dp.y));
+        reinterpret_cast<C*>(sl.v[f] + (size_t)line * nx)[n] = vn;
+        buf[n * TWP + f * LPB + l] = vn;
+      }
+    });
+    if (has_next) {
+      const Slot<T> sn = item_slot(next);
+      const int n0 = (next % ngroups) * LPB;
+      prefetch_v(sn, n0, min(LPB, a.d.nlines - n0));
+    }
+    __syncthreads();
+    lds_fft<T, M, NC, TWP, X_NT, false>(buf, a.tb.tw_x);
+    r2c_post<T, M, TWP, NC>(buf, a.tb.rtw);
+    __syncthreads();
+    x_store_spectra<T, M, LPB, TWP, 3>(buf, sl.spec, 0, l0, nl, px);
+    __syncthreads();
+  }
 }
 
 enum XMode { XM_FWD = 0, XM_PAIR = 1, XM_TRONLY = 2, XM_ADJONLY = 3 };
@@ -425,7 +665,7 @@ template <typename T> struct X2Args {
   T* tape;               // [B][nt][n_bnd] or null
   const T* adj_src;      // [B][nt][n_rec]: a^j (reversed running sum of the residual)
   int tape_row;          // TR: tape row imposed in this step
-  int tr_zero_state;     // TR: previous state is zero (initialisation)
+  int tr_state_mode;     // TR initialisation: 0 step, 1 zero state, 2 keep densities
   T* ring;               // [B][3][n_gam]
   int ring_a, ring_b, ring_c;
   double* gacc;          // [B][n_gam]
@@ -473,30 +713,31 @@ __device__ __forceinline__ int local_line(const int32_t* off, int l0, int nl, in
 // Density update of one simulation slot for the workgroup's lines: C2R of
 // d-_a v_a, rho_a <- L_a (L_a rho_a - dt rho0 d-_a v_a) (+ injection, or
 // Dirichlet on dGamma), p = c0^2 sum_a rho_a written to column pcol of buf.
+// state_mode: 0 = one density step, 1 = zero state (TR start from the tape
+// only), 2 = keep the stored densities (TR start from the final forward state)
 template <typename T, int M, int LPB, int TWP, int TWPP, int KIND>
 __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx& si, const Slot<T>& sl, int b,
-                                               int l0, int nl, bool zero_state, int pcol, cplx<T>* buf,
+                                               int l0, int nl, int state_mode, int pcol, cplx<T>* buf,
                                                cplx<T>* bufp, cplx<T>* spv, uint8_t* spm) {
+  const bool zero_state = state_mode == 1;
+  const bool no_step = state_mode != 0;
   using C = cplx<T>;
   constexpr int NC = 3 * LPB;
   const int nx = a.d.nx;
   const size_t px = a.d.px;
   const T* cb = a.c + (size_t)b * a.d.nfield;
   // prefetch c0 and the split densities: in flight during the C2R transforms
-  constexpr int EB = (M * LPB + X_NT - 1) / X_NT;
+  constexpr int EB = Lanes<LPB, M>::NI;
   C cc[EB], rr[EB][3];
-#pragma unroll
-  for (int i = 0; i < EB; ++i) {
-    const int e = (int)threadIdx.x + i * X_NT;
-    const int l = e / M, n = e % M;
-    const bool ok = (e < M * LPB) && (l < nl);
+  lanes2d<LPB, M>([&](int i, int l, int n) {
+    const bool ok = l < nl;
     const size_t lo = (size_t)(l0 + l) * nx;
     cc[i] = ok ? reinterpret_cast<const C*>(cb + lo)[n] : cmake<C>((T)0, (T)0);
 #pragma unroll
     for (int f = 0; f < 3; ++f)
       rr[i][f] = (ok && !zero_state) ? reinterpret_cast<const C*>(sl.rho[f] + lo)[n] : cmake<C>((T)0, (T)0);
-  }
-  if (!zero_state) x_load_spectra<T, M, LPB, TWP, 3>(buf, sl.spec, 0, l0, nl, px);
+  });
+  if (!no_step) x_load_spectra<T, M, LPB, TWP, 3>(buf, sl.spec, 0, l0, nl, px);
   for (int e = threadIdx.x; e < M * LPB; e += X_NT) {
     spv[e] = cmake<C>((T)0, (T)0);
     if (KIND == SP_DIRICHLET) { spm[2 * e] = 0; spm[2 * e + 1] = 0; }
@@ -537,18 +778,15 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx
       spm[q] = 1;
     }
   }
-  if (!zero_state) {
+  if (!no_step) {
     c2r_pre<T, M, TWP, NC>(buf, a.tb.rtw);
     __syncthreads();
     lds_fft<T, M, NC, TWP, X_NT, true>(buf, a.tb.tw_x);
   } else {
     __syncthreads();
   }
-#pragma unroll
-  for (int i = 0; i < EB; ++i) {
-    const int e = (int)threadIdx.x + i * X_NT;
-    const int l = e / M, n = e % M;
-    if (e >= M * LPB || l >= nl) continue;
+  lanes2d<LPB, M>([&](int i, int l, int n) {
+    if (l >= nl) return;
     const int line = l0 + l;
     const int yy = line % a.d.ny, zz = line / a.d.ny;
     const C c2 = cc[i];
@@ -560,6 +798,8 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx
       C rn;
       if (zero_state) {
         rn = cmake<C>((T)0, (T)0);
+      } else if (no_step) {
+        rn = rr[i][f];
       } else {
         const C dv = buf[n * TWP + f * LPB + l];
         T lx, ly;
@@ -578,7 +818,7 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx
       sum = cadd(sum, rn);
     }
     bufp[n * TWPP + pcol + l] = cmake<C>(c2.x * c2.x * sum.x, c2.y * c2.y * sum.y);
-  }
+  });
   __syncthreads();
 }
 
@@ -619,7 +859,7 @@ __global__ void __launch_bounds__(X_NT) k_x_density(X2Args<T> a) {
   const StepIdx si = step_indices<T, MODE>(a);
 
   if (MODE == XM_FWD) {
-    density_update<T, M, LPB, TWP, TWPP, SP_SOURCE>(a, si, s_tr, b, l0, nl, false, PA, buf, bufp, spv, spm);
+    density_update<T, M, LPB, TWP, TWPP, SP_SOURCE>(a, si, s_tr, b, l0, nl, 0, PA, buf, bufp, spv, spm);
     // sensors f^n = M p and boundary tape g^n = p(dGamma)
     const int i0 = a.g.rec_off[l0], i1 = a.g.rec_off[l0 + nl];
     for (int i = i0 + (int)threadIdx.x; i < i1; i += X_NT) {
@@ -637,10 +877,10 @@ __global__ void __launch_bounds__(X_NT) k_x_density(X2Args<T> a) {
     }
   }
   if (MODE == XM_PAIR || MODE == XM_ADJONLY) {
-    density_update<T, M, LPB, TWP, TWPP, SP_ADJOINT>(a, si, s_adj, b, l0, nl, false, PA, buf, bufp, spv, spm);
+    density_update<T, M, LPB, TWP, TWPP, SP_ADJOINT>(a, si, s_adj, b, l0, nl, 0, PA, buf, bufp, spv, spm);
   }
   if (MODE == XM_PAIR || MODE == XM_TRONLY) {
-    density_update<T, M, LPB, TWP, TWPP, SP_DIRICHLET>(a, si, s_tr, b, l0, nl, a.tr_zero_state != 0, PT, buf, bufp,
+    density_update<T, M, LPB, TWP, TWPP, SP_DIRICHLET>(a, si, s_tr, b, l0, nl, a.tr_state_mode, PT, buf, bufp,
                                                        spv, spm);
   }
   if (MODE != XM_FWD) {
@@ -688,6 +928,13 @@ __global__ void k_fill(T* p, long long n, T v) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
     p[i] = v;
+}
+
+template <typename T>
+__global__ void k_scale(T* p, long long n, T v) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] *= v;
 }
 
 // Residual r^n = f^n - f^delta_n (or a given residual), adjoint source
@@ -764,11 +1011,10 @@ __global__ void __launch_bounds__(X_NT) k_x_r2c(XArgs<T> a, const T* in, int f) 
   const int l0 = blockIdx.x * LPB;
   const int nl = min(LPB, a.d.nlines - l0);
   const Slot<T> sl = a.slots[a.slot0];
-  for (int e = threadIdx.x; e < M * LPB; e += X_NT) {
-    const int l = e / M, n = e % M;
+  lanes2d<LPB, M>([&](int, int l, int n) {
     buf[n * TWP + l] = (l < nl) ? reinterpret_cast<const C*>(in + (size_t)(l0 + l) * a.d.nx)[n]
                                 : cmake<C>((T)0, (T)0);
-  }
+  });
   __syncthreads();
   lds_fft<T, M, LPB, TWP, X_NT, false>(buf, a.tb.tw_x);
   r2c_post<T, M, TWP, LPB>(buf, a.tb.rtw);
@@ -792,10 +1038,9 @@ __global__ void __launch_bounds__(X_NT) k_x_c2r(XArgs<T> a, T* out, int f) {
   c2r_pre<T, M, TWP, LPB>(buf, a.tb.rtw);
   __syncthreads();
   lds_fft<T, M, LPB, TWP, X_NT, true>(buf, a.tb.tw_x);
-  for (int e = threadIdx.x; e < M * LPB; e += X_NT) {
-    const int l = e / M, n = e % M;
+  lanes2d<LPB, M>([&](int, int l, int n) {
     if (l < nl) reinterpret_cast<C*>(out + (size_t)(l0 + l) * a.d.nx)[n] = buf[n * TWP + l];
-  }
+  });
 }
 
 }  // namespace fwi

@@ -39,6 +39,27 @@ def rademacher(seed: int, n: int) -> np.ndarray:
     return out
 
 
+def delays(seed: int, n: int, tau_steps: int) -> np.ndarray:
+    """Whole-step delays of delayed source encoding (host, bit-exact); int32 [n]."""
+    lib = L.load()
+    out = np.empty(n, dtype=np.int32)
+    _check(lib.fwi_delays(ctypes.c_uint64(seed & ((1 << 64) - 1)), n, int(tau_steps),
+                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))), "fwi_delays")
+    return out
+
+
+def delayed_signals(src_sig, delays_steps, nt_total: int) -> np.ndarray:
+    """Per-source signals [nt_total, n_src] with source i shifted by delays_steps[i]
+    (eq. DelaySE: s_i(t - d_i tau)); zero before the shift and after the end."""
+    src = np.asarray(src_sig)
+    nt, ns = src.shape
+    out = np.zeros((nt_total, ns), dtype=src.dtype)
+    for i, d in enumerate(np.asarray(delays_steps)):
+        m = max(0, min(nt, nt_total - int(d)))
+        out[int(d):int(d) + m, i] = src[:m, i]
+    return out
+
+
 def _params(shape, dx, dt, nt, c_ref, c_min, c_max, rho0, pml, pml_alpha, precision, batch):
     nz, ny, nx = shape
     p = L.FwiParams()
@@ -109,6 +130,7 @@ class Handle:
         self.n_cells = self.shape[0] * self.shape[1] * self.shape[2]
         self.tape_token = 0   # bumps whenever a call overwrites the saved tape
         self.use_graph = False
+        self.tr_final_state = False   # FWI_TR_FINAL_STATE for gradient / backward
         with torch.cuda.device(self.device):
             _check(self._lib.fwi_create(ctypes.byref(p), ctypes.byref(geo.c), int(device),
                                         ctypes.byref(self._h)), "fwi_create")
@@ -170,6 +192,7 @@ class Handle:
         else:
             grad = torch.empty((B, *self.shape), device=self.device, dtype=self.dtype)
         flags = (L.FWI_CHECK_INPUT if check else 0) | (L.FWI_GRAPH if self.use_graph else 0)
+        flags |= L.FWI_TR_FINAL_STATE if self.tr_final_state else 0
         self.tape_token += 1
         _check(self._lib.fwi_gradient(self._h, B, c.data_ptr(), src.data_ptr(), w.data_ptr(), obs.data_ptr(),
                                       mis.data_ptr(), grad.data_ptr(), flags, self._stream()), "fwi_gradient")
@@ -183,7 +206,7 @@ class Handle:
         r = self._t(residual, (self.nt, self.n_rec))
         mis = torch.empty((B,), device=self.device, dtype=torch.float64)
         grad = torch.empty((B, *self.shape), device=self.device, dtype=self.dtype)
-        flags = L.FWI_GRAPH if self.use_graph else 0
+        flags = (L.FWI_GRAPH if self.use_graph else 0) | (L.FWI_TR_FINAL_STATE if self.tr_final_state else 0)
         _check(self._lib.fwi_backward(self._h, B, c.data_ptr(), r.data_ptr(), mis.data_ptr(), grad.data_ptr(),
                                       flags, self._stream()), "fwi_backward")
         return mis, grad

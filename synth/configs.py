@@ -292,17 +292,18 @@ def make_config(name: str, index: int = 0, nt: Optional[int] = None,
 
 def make_small(shape=(24, 28, 32), pml=3, nt=48, dx=0.5e-3, n_src=2, n_rec=12,
                layer=2, seed=7, precision=8, periodic=False, c_ref=C_MAX,
-               homogeneous=False, f0=None) -> Problem:
+               homogeneous=False, f0=None, r_transducer=None, r_gamma=None) -> Problem:
     """A small problem for pins and parity: ball-shaped Gamma in the centre,
     sources and receivers on a sphere around it, seeded blobs inside Gamma.
 
-    ``periodic=True`` removes the absorbing layer (PML size 0).
+    ``periodic=True`` removes the absorbing layer (PML size 0).  The sphere
+    radii default to the largest that fit; they can be given (in cells).
     """
     nz, ny, nx = shape
     p = 0 if periodic else pml
     ctr = ((nx - 1) / 2.0, (ny - 1) / 2.0, (nz - 1) / 2.0)
-    r_t = min(nx, ny, nz) / 2.0 - p - 1.5
-    r_g = max(2.0, r_t - 3.0)
+    r_t = min(nx, ny, nz) / 2.0 - p - 1.5 if r_transducer is None else float(r_transducer)
+    r_g = max(2.0, r_t - 3.0) if r_gamma is None else float(r_gamma)
     pos = golden_section_cap(2 * max(n_src, n_rec), ctr, r_t, 180.0, +1.0)
     ijk = snap_to_voxels(pos)
     src = np.ascontiguousarray(ijk[0::2][:n_src])

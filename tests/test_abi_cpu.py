@@ -63,3 +63,22 @@ def test_full_size_workspace_fits_one_gpu():
     # tape (2200 steps x |dGamma|) + two slots of state and spectra
     tape = 2200 * int(prob.boundary.sum()) * 4
     assert tape < nbytes < 24e9
+
+
+@pytest.mark.parametrize("seed,tau", [(0, 0), (7, 100), (1005, 2200)])
+def test_delays_bit_exact_with_oracle(seed, tau):
+    from paper_2102_00755_amd.fwi import delays
+    got = delays(seed, 1024, tau)
+    want = oracle.delays(seed, 1024, tau)
+    assert np.array_equal(got, want)
+    assert got.min() >= 0 and got.max() <= tau
+    if tau:
+        assert abs(got.mean() / tau - 0.5) < 0.05     # d_i ~ U[0,1)
+
+
+def test_delayed_signals_shift():
+    from paper_2102_00755_amd.fwi import delayed_signals
+    S = np.arange(12, dtype=np.float64).reshape(6, 2) + 1
+    out = delayed_signals(S, [0, 3], 8)
+    assert np.array_equal(out[:6, 0], S[:, 0]) and np.all(out[6:, 0] == 0)
+    assert np.all(out[:3, 1] == 0) and np.array_equal(out[3:8, 1], S[:5, 1])

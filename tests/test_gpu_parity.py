@@ -134,3 +134,26 @@ def test_batched_equals_individual():
         assert float(m1[0]) == float(mb[i])
     h1.close()
     h3.close()
+
+
+@pytest.mark.parametrize("precision,tol", [(8, 1e-9), (4, 1e-3)])
+def test_tr_gradient_from_final_state_matches_oracle(precision, tol):
+    # reading 11: TR started from (rho^N, -v^{N+1/2}) instead of the zero interior
+    shape = SHAPES[1]
+    prob = make_small(shape=shape, nt=50, n_src=3, n_rec=12, layer=2, precision=precision)
+    w, S = _inputs(prob)
+    sch = ks.scheme_for(prob)
+    obs = random_traces(prob.nt, prob.n_rec, seed=5, scale=1e-3)
+    D, G, _ = ks.tr_gradient(sch, prob.c_eval, prob.src_ijk, S, w, prob.rec_ijk, obs, prob.gamma,
+                             prob.boundary, prob.nt, tr_init="final_state")
+    D0, G0, _ = ks.tr_gradient(sch, prob.c_eval, prob.src_ijk, S, w, prob.rec_ijk, obs, prob.gamma,
+                               prob.boundary, prob.nt)
+    g = prob.gamma.astype(bool)
+    assert rel(G0[g], G[g]) > 10 * tol          # the two initialisations differ
+    h = handle(prob, precision)
+    h.tr_final_state = True
+    mis, grad = h.gradient(torch.from_numpy(prob.c_eval), torch.from_numpy(S), torch.from_numpy(w),
+                           torch.from_numpy(obs))
+    assert abs(float(mis[0]) - D) <= 1e-6 * D
+    assert rel(grad[0].cpu().numpy()[g], G[g]) < tol
+    h.close()
