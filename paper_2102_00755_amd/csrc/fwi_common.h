@@ -31,6 +31,24 @@ template <bool INV, typename C> __device__ __forceinline__ C crot(C a) {
   return INV ? cmake<C>(-a.y, a.x) : cmake<C>(a.y, -a.x);
 }
 
+// Global-memory loads and stores through address space 1.  Pointers read
+// from memory (the slot table) are generic to the compiler, and generic
+// (flat) accesses count against the LDS wait counter as well: every LDS wait
+// of a transform would then also wait for the HBM loads still in flight.
+#define FWI_GAS __attribute__((address_space(1)))
+template <int N> struct gword;
+template <> struct gword<4> { typedef unsigned int type; };
+template <> struct gword<8> { typedef unsigned int type __attribute__((ext_vector_type(2))); };
+template <> struct gword<16> { typedef unsigned int type __attribute__((ext_vector_type(4))); };
+template <typename V> __device__ __forceinline__ V gld(const V* p) {
+  using W = typename gword<sizeof(V)>::type;
+  return __builtin_bit_cast(V, *(const FWI_GAS W*)p);
+}
+template <typename V> __device__ __forceinline__ void gst(V* p, V v) {
+  using W = typename gword<sizeof(V)>::type;
+  *(FWI_GAS W*)p = __builtin_bit_cast(W, v);
+}
+
 // Operator tables of one handle (device pointers), all built on the host in
 // FP64 and rounded once to T.
 template <typename T> struct Tables {

@@ -90,21 +90,25 @@ __device__ __forceinline__ int slot_of(int i, int slot0, int na, int slot1) {
   return i < na ? slot0 + i : slot1 + (i - na);
 }
 
-// All global loads of a thread are issued before the first LDS store so that
-// the whole tile is in flight at once (memory-level parallelism is what
-// bounds a streaming pass).
+// Whole tiles are moved: the spectrum pitch px is a multiple of TW, so the
+// padding columns of the last tile (kx > M) are in bounds.  They are
+// transformed with the valid columns (columns never mix) and never read by
+// the x passes.  Loads are unpredicated so that a thread's loads are all in
+// flight before the first wait, and full 64-byte row segments are written.
 template <typename T, int L, int TW, int NT>
-__device__ __forceinline__ void tile_load(cplx<T>* buf, const cplx<T>* g, size_t rstride, int ncol) {
-  using C = cplx<T>;
+__device__ __forceinline__ void tile_prefetch(cplx<T>* tmp, const cplx<T>* g, size_t rstride) {
   constexpr int E = L * TW;
   constexpr int EPT = (E + NT - 1) / NT;
-  C tmp[EPT];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    const int e = (int)threadIdx.x + i * NT;
-    const int r = e / TW, c = e % TW;
-    tmp[i] = (c < ncol && (E % NT == 0 || e < E)) ? g[(size_t)r * rstride + c] : cmake<C>((T)0, (T)0);
+    const int e = min((int)threadIdx.x + i * NT, E - 1);
+    tmp[i] = gld(g + (size_t)(e / TW) * rstride + e % TW);
   }
+}
+template <typename T, int L, int TW, int NT>
+__device__ __forceinline__ void tile_commit(cplx<T>* buf, const cplx<T>* tmp) {
+  constexpr int E = L * TW;
+  constexpr int EPT = (E + NT - 1) / NT;
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int e = (int)threadIdx.x + i * NT;
@@ -112,161 +116,45 @@ __device__ __forceinline__ void tile_load(cplx<T>* buf, const cplx<T>* g, size_t
   }
 }
 template <typename T, int L, int TW, int NT>
-__device__ __forceinline__ void tile_store(const cplx<T>* buf, cplx<T>* g, size_t rstride, int ncol) {
+__device__ __forceinline__ void tile_store(const cplx<T>* buf, cplx<T>* g, size_t rstride) {
   constexpr int E = L * TW;
   constexpr int EPT = (E + NT - 1) / NT;
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int e = (int)threadIdx.x + i * NT;
-    const int r = e / TW, c = e % TW;
-    if (c < ncol && (E % NT == 0 || e < E)) g[(size_t)r * rstride + c] = buf[e];
+    if (E % NT == 0 || e < E) gst(g + (size_t)(e / TW) * rstride + e % TW, buf[e]);
   }
 }
 
-// ---- persistent axis passes -------------------------------------------------
-// Each workgroup walks the tile list with stride gridDim.x.  The global loads
-// of the next tile are issued into registers right after the current tile has
-// been written to LDS, so they are in flight during the current tile's FFTs
-// and stores (one tile of prefetch per workgroup).
-template <typename T> struct TileRef {
-  cplx<T>* g;   // first element of the tile in its field
-  int ncol;     // valid columns (ragged last tile)
-  int kx0;      // first kx column
-  int outer;    // z (y pass) or y (z pass)
-  int s, f;     // slot and field
+// Twiddle table W_N^m, m < N, staged in LDS by each workgroup: the stages of
+// a transform then read their twiddles with the butterfly operands instead
+// of waiting for an L2 round trip per stage.  Issued with the tile loads.
+template <int N, int NT> struct TwRegs {
+  static constexpr int N_PER = (N + NT - 1) / NT;
 };
-
-template <typename T, int TW>
-__device__ __forceinline__ TileRef<T> tile_ref(const AxisArgs<T>& a, int item, int nouter, int nf_tile,
-                                               size_t outer_stride) {
-  const int ntx = (a.d.M + TW) / TW;
-  const int per = ntx * nouter;
-  const int si = item / per;
-  const int rem = item % per;
-  const int outer = rem / ntx, tile = rem % ntx;
-  TileRef<T> t;
-  t.s = slot_of(si / nf_tile, a.slot0, a.na, a.slot1);
-  t.f = a.f0 + si % nf_tile;
-  t.kx0 = tile * TW;
-  t.g = a.slots[t.s].spec[t.f] + (size_t)outer * outer_stride + (size_t)t.kx0;
-  t.ncol = min(TW, a.d.M + 1 - t.kx0);
-  t.outer = outer;
-  return t;
-}
-
-template <typename T, int L, int TW, int NT>
-__device__ __forceinline__ void tile_prefetch(cplx<T>* pre, const cplx<T>* g, int ncol, size_t rstride) {
-  using C = cplx<T>;
-  constexpr int E = L * TW;
-  constexpr int EPT = (E + NT - 1) / NT;
+template <typename T, int N, int NT>
+__device__ __forceinline__ void tw_prefetch(cplx<T>* tt, const cplx<T>* tw) {
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) {
+  for (int i = 0; i < TwRegs<N, NT>::N_PER; ++i) tt[i] = gld(tw + min((int)threadIdx.x + i * NT, N - 1));
+}
+template <typename T, int N, int NT>
+__device__ __forceinline__ void tw_commit(cplx<T>* twl, const cplx<T>* tt) {
+#pragma unroll
+  for (int i = 0; i < TwRegs<N, NT>::N_PER; ++i) {
     const int e = (int)threadIdx.x + i * NT;
-    const int r = e / TW, c = e % TW;
-    pre[i] = (c < ncol && (E % NT == 0 || e < E)) ? g[(size_t)r * rstride + c] : cmake<C>((T)0, (T)0);
+    if (N % NT == 0 || e < N) twl[e] = tt[i];
   }
 }
+
+// Tile and twiddles into LDS (loads of both in flight together).
 template <typename T, int L, int TW, int NT>
-__device__ __forceinline__ void tile_commit(cplx<T>* buf, const cplx<T>* pre) {
-  constexpr int E = L * TW;
-  constexpr int EPT = (E + NT - 1) / NT;
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = (int)threadIdx.x + i * NT;
-    if (E % NT == 0 || e < E) buf[e] = pre[i];
-  }
-}
-
-// kappa * scale * i k_f exp(sign i k_f dx / 2) at row r (kz), column kx, y
-template <typename T>
-__device__ __forceinline__ cplx<T> zmult(const AxisArgs<T>& a, const cplx<T>* const* sfac, int f, int kx, int y,
-                                         int r, T ky2) {
-  const T u = a.kap_a * (a.tb.ksq[0][kx] + ky2 + a.tb.ksq[2][r]);
-  const T kap = sinc_u(u) * a.scale;
-  const cplx<T> sf = (f == 0) ? sfac[0][kx] : ((f == 1) ? sfac[1][y] : sfac[2][r]);
-  return cscale(sf, kap);
-}
-
-enum AxisKind { AK_Y = 0, AK_ZMINUS = 1, AK_ZPLUS = 2 };
-
-// Persistent axis pass over nitems tiles:
-//   AK_Y      in-place FFT along y (forward or inverse by INV) of nf fields
-//   AK_ZMINUS field f -> F_z^-1 m-_f F_z field f                (Z1)
-//   AK_ZPLUS  field 0 -> fields 0,1,2 = F_z^-1 m+_a F_z field 0  (Z2)
-template <typename T, int L, int KIND, bool INV>
-__global__ void __launch_bounds__(axis_nt(L, axis_tw<T>()))
-k_axis_persist(AxisArgs<T> a, int nitems) {
-  using C = cplx<T>;
-  constexpr int TW = axis_tw<T>();
-  constexpr int NT = axis_nt(L, TW);
-  constexpr int E = L * TW;
-  constexpr int EPT = (E + NT - 1) / NT;
-  __shared__ C buf[L * TW];
-  const size_t px = a.d.px;
-  const int nouter = (KIND == AK_Y) ? a.d.nz : a.d.ny;
-  const size_t ostride = (KIND == AK_Y) ? (size_t)a.d.ny * px : px;
-  const size_t rstride = (KIND == AK_Y) ? px : (size_t)a.d.ny * px;
-  const int nf_tile = (KIND == AK_ZPLUS) ? 1 : a.nf;
-  C pre[EPT];
-  int item = blockIdx.x;
-  if (item < nitems) {
-    const TileRef<T> t = tile_ref<T, TW>(a, item, nouter, nf_tile, ostride);
-    tile_prefetch<T, L, TW, NT>(pre, t.g, t.ncol, rstride);
-  }
-  for (; item < nitems; item += gridDim.x) {
-    const TileRef<T> t = tile_ref<T, TW>(a, item, nouter, nf_tile, ostride);
-    tile_commit<T, L, TW, NT>(buf, pre);
-    __syncthreads();
-    const int next = item + gridDim.x;
-    if (next < nitems) {
-      const TileRef<T> tn = tile_ref<T, TW>(a, next, nouter, nf_tile, ostride);
-      tile_prefetch<T, L, TW, NT>(pre, tn.g, tn.ncol, rstride);
-    }
-    if (KIND == AK_Y) {
-      lds_fft<T, L, TW, TW, NT, INV>(buf, a.tb.tw_y);
-      tile_store<T, L, TW, NT>(buf, t.g, rstride, t.ncol);
-    } else if (KIND == AK_ZMINUS) {
-      lds_fft<T, L, TW, TW, NT, false>(buf, a.tb.tw_z);
-      const T ky2 = a.tb.ksq[1][t.outer];
-#pragma unroll
-      for (int i = 0; i < EPT; ++i) {
-        const int e = (int)threadIdx.x + i * NT;
-        const int r = e / TW, c = e % TW;
-        if ((E % NT == 0 || e < E) && c < t.ncol)
-          buf[e] = cmul(zmult<T>(a, a.tb.sfac_m, t.f, t.kx0 + c, t.outer, r, ky2), buf[e]);
-      }
-      __syncthreads();
-      lds_fft<T, L, TW, TW, NT, true>(buf, a.tb.tw_z);
-      tile_store<T, L, TW, NT>(buf, t.g, rstride, t.ncol);
-    } else {
-      lds_fft<T, L, TW, TW, NT, false>(buf, a.tb.tw_z);
-      const T ky2 = a.tb.ksq[1][t.outer];
-      C xr[EPT];
-#pragma unroll
-      for (int i = 0; i < EPT; ++i) {
-        const int e = (int)threadIdx.x + i * NT;
-        if (E % NT == 0 || e < E) xr[i] = buf[e];
-      }
-      const size_t off = (size_t)(t.g - a.slots[t.s].spec[0]);
-#pragma unroll
-      for (int f = 0; f < 3; ++f) {
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < EPT; ++i) {
-          const int e = (int)threadIdx.x + i * NT;
-          const int r = e / TW, c = e % TW;
-          if (E % NT == 0 || e < E) {
-            const int kx = min(t.kx0 + c, a.d.M);
-            buf[e] = cmul(zmult<T>(a, a.tb.sfac_p, f, kx, t.outer, r, ky2), xr[i]);
-          }
-        }
-        __syncthreads();
-        lds_fft<T, L, TW, TW, NT, true>(buf, a.tb.tw_z);
-        tile_store<T, L, TW, NT>(buf, a.slots[t.s].spec[f] + off, rstride, t.ncol);
-      }
-    }
-    __syncthreads();
-  }
+__device__ __forceinline__ void tile_load(cplx<T>* buf, const cplx<T>* g, size_t rstride, cplx<T>* twl,
+                                          const cplx<T>* tw) {
+  cplx<T> tmp[(L * TW + NT - 1) / NT], tt[TwRegs<L, NT>::N_PER];
+  tile_prefetch<T, L, TW, NT>(tmp, g, rstride);
+  tw_prefetch<T, L, NT>(tt, tw);
+  tile_commit<T, L, TW, NT>(buf, tmp);
+  tw_commit<T, L, NT>(twl, tt);
 }
 
 // Y pass: in-place FFT along y of nf fields per slot.  L == ny.
@@ -277,18 +165,62 @@ k_axis_y(AxisArgs<T> a) {
   constexpr int TW = axis_tw<T>();
   constexpr int NT = axis_nt(L, TW);
   __shared__ C buf[L * TW];
-  const int ntx = (a.d.M + TW) / TW;
+  __shared__ C twl[L];
+  const int ntx = a.d.px / TW;   // tiles per row: px is a multiple of TW
   const int tile = blockIdx.x % ntx;
   const int z = blockIdx.x / ntx;
   const int s = slot_of(blockIdx.y / a.nf, a.slot0, a.na, a.slot1);
   const int f = a.f0 + blockIdx.y % a.nf;
   const size_t px = a.d.px;
   C* g = a.slots[s].spec[f] + (size_t)z * L * px + (size_t)tile * TW;
-  const int ncol = min(TW, a.d.M + 1 - tile * TW);
-  tile_load<T, L, TW, NT>(buf, g, px, ncol);
+  tile_load<T, L, TW, NT>(buf, g, px, twl, a.tb.tw_y);
   __syncthreads();
-  lds_fft<T, L, TW, TW, NT, INV>(buf, a.tb.tw_y);
-  tile_store<T, L, TW, NT>(buf, g, px, ncol);
+  lds_fft<T, L, TW, TW, NT, INV>(buf, twl);
+  tile_store<T, L, TW, NT>(buf, g, px);
+}
+
+// k-space multipliers of the elements a thread owns in a z tile: thread t
+// owns rows r_i = t / TW + i NT / TW of column c = t % TW (NT is a multiple
+// of TW), so kx is fixed per thread.  The tables are read before the tile's
+// data arrives (their latency overlaps the tile load).
+template <typename T, int L, int TW, int NT>
+__device__ __forceinline__ void z_kappa(const AxisArgs<T>& a, int kx, int y, T* kap) {
+  static_assert(NT % TW == 0, "z tile: NT must be a multiple of TW");
+  constexpr int EPT = (L * TW + NT - 1) / NT;
+  const T base = a.tb.ksq[0][kx] + a.tb.ksq[1][y];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int r = (int)threadIdx.x / TW + i * (NT / TW);
+    if ((L * TW) % NT == 0 || r < L) kap[i] = sinc_u(a.kap_a * (base + a.tb.ksq[2][r])) * a.scale;
+  }
+}
+// kappa * scale * s_f with the shift factor s_f = i k_f exp(+-i k_f dx / 2)
+// of field f (sfac = sfac_p or sfac_m)
+template <typename T, int L, int TW, int NT>
+__device__ __forceinline__ void z_mult(const AxisArgs<T>& a, const cplx<T>* const* sfac, int f, int kx, int y,
+                                       const T* kap, cplx<T>* m) {
+  constexpr int EPT = (L * TW + NT - 1) / NT;
+  if (f == 2) {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int r = (int)threadIdx.x / TW + i * (NT / TW);
+      if ((L * TW) % NT == 0 || r < L) m[i] = cscale(sfac[2][r], kap[i]);
+    }
+  } else {
+    const cplx<T> sf = (f == 0) ? sfac[0][kx] : sfac[1][y];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) m[i] = cscale(sf, kap[i]);
+  }
+}
+template <typename T, int L, int TW, int NT>
+__device__ __forceinline__ void z_apply(cplx<T>* buf, const cplx<T>* m, const cplx<T>* x) {
+  constexpr int E = L * TW;
+  constexpr int EPT = (E + NT - 1) / NT;
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = (int)threadIdx.x + i * NT;
+    if (E % NT == 0 || e < E) buf[e] = cmul(m[i], x ? x[i] : buf[e]);
+  }
 }
 
 // Z pass of the velocity divergence terms: field f -> F_z^-1 m-_f F_z field f
@@ -299,8 +231,10 @@ k_axis_z_minus(AxisArgs<T> a) {
   using C = cplx<T>;
   constexpr int TW = axis_tw<T>();
   constexpr int NT = axis_nt(L, TW);
+  constexpr int EPT = (L * TW + NT - 1) / NT;
   __shared__ C buf[L * TW];
-  const int ntx = (a.d.M + TW) / TW;
+  __shared__ C twl[L];
+  const int ntx = a.d.px / TW;   // tiles per row: px is a multiple of TW
   const int tile = blockIdx.x % ntx;
   const int y = blockIdx.x / ntx;
   const int s = slot_of(blockIdx.y / a.nf, a.slot0, a.na, a.slot1);
@@ -308,26 +242,18 @@ k_axis_z_minus(AxisArgs<T> a) {
   const size_t px = a.d.px;
   const size_t rstride = (size_t)a.d.ny * px;
   C* g = a.slots[s].spec[f] + (size_t)y * px + (size_t)tile * TW;
-  const int ncol = min(TW, a.d.M + 1 - tile * TW);
-  tile_load<T, L, TW, NT>(buf, g, rstride, ncol);
+  const int kx = min(tile * TW + (int)threadIdx.x % TW, a.d.M);
+  T kap[EPT];
+  C m[EPT];
+  z_kappa<T, L, TW, NT>(a, kx, y, kap);
+  z_mult<T, L, TW, NT>(a, a.tb.sfac_m, f, kx, y, kap, m);
+  tile_load<T, L, TW, NT>(buf, g, rstride, twl, a.tb.tw_z);
   __syncthreads();
-  lds_fft<T, L, TW, TW, NT, false>(buf, a.tb.tw_z);
-  const T ky2 = a.tb.ksq[1][y];
-  const C sfy = a.tb.sfac_m[1][y];
-#pragma unroll 4
-  for (int e = threadIdx.x; e < L * TW; e += NT) {
-    const int r = e / TW, c = e % TW;
-    if (c < ncol) {
-      const int kx = tile * TW + c;
-      const T u = a.kap_a * (a.tb.ksq[0][kx] + ky2 + a.tb.ksq[2][r]);
-      const T kap = sinc_u(u) * a.scale;
-      const C sf = (f == 0) ? a.tb.sfac_m[0][kx] : ((f == 1) ? sfy : a.tb.sfac_m[2][r]);
-      buf[e] = cscale(cmul(sf, buf[e]), kap);
-    }
-  }
+  lds_fft<T, L, TW, TW, NT, false>(buf, twl);
+  z_apply<T, L, TW, NT>(buf, m, nullptr);
   __syncthreads();
-  lds_fft<T, L, TW, TW, NT, true>(buf, a.tb.tw_z);
-  tile_store<T, L, TW, NT>(buf, g, rstride, ncol);
+  lds_fft<T, L, TW, TW, NT, true>(buf, twl);
+  tile_store<T, L, TW, NT>(buf, g, rstride);
 }
 
 // Z pass of the pressure gradient: field 0 (p_hat) -> fields 0,1,2 =
@@ -340,49 +266,37 @@ k_axis_z_plus(AxisArgs<T> a) {
   constexpr int NT = axis_nt(L, TW);
   constexpr int EPT = (L * TW + NT - 1) / NT;
   __shared__ C buf[L * TW];
-  const int ntx = (a.d.M + TW) / TW;
+  __shared__ C twl[L];
+  const int ntx = a.d.px / TW;   // tiles per row: px is a multiple of TW
   const int tile = blockIdx.x % ntx;
   const int y = blockIdx.x / ntx;
   const int s = slot_of(blockIdx.y, a.slot0, a.na, a.slot1);
   const size_t px = a.d.px;
   const size_t rstride = (size_t)a.d.ny * px;
   const size_t off = (size_t)y * px + (size_t)tile * TW;
-  const Slot<T> sl = a.slots[s];
-  const int ncol = min(TW, a.d.M + 1 - tile * TW);
-  tile_load<T, L, TW, NT>(buf, sl.spec[0] + off, rstride, ncol);
+  const int kx = min(tile * TW + (int)threadIdx.x % TW, a.d.M);
+  C* const s0 = a.slots[s].spec[0];
+  C* const s1 = a.slots[s].spec[1];
+  C* const s2 = a.slots[s].spec[2];
+  T kap[EPT];
+  z_kappa<T, L, TW, NT>(a, kx, y, kap);
+  tile_load<T, L, TW, NT>(buf, s0 + off, rstride, twl, a.tb.tw_z);
   __syncthreads();
-  lds_fft<T, L, TW, TW, NT, false>(buf, a.tb.tw_z);
-  C xr[EPT];
-  T kr[EPT];
-  const T ky2 = a.tb.ksq[1][y];
+  lds_fft<T, L, TW, TW, NT, false>(buf, twl);
+  C xr[EPT], m[EPT];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * NT;
-    if (e < L * TW) {
-      const int r = e / TW, c = e % TW;
-      xr[i] = buf[e];
-      const int kx = min(tile * TW + c, a.d.M);
-      const T u = a.kap_a * (a.tb.ksq[0][kx] + ky2 + a.tb.ksq[2][r]);
-      kr[i] = sinc_u(u) * a.scale;
-    }
+    const int e = (int)threadIdx.x + i * NT;
+    if ((L * TW) % NT == 0 || e < L * TW) xr[i] = buf[e];
   }
-  const C sfy = a.tb.sfac_p[1][y];
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
+    z_mult<T, L, TW, NT>(a, a.tb.sfac_p, f, kx, y, kap, m);
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int e = threadIdx.x + i * NT;
-      if (e < L * TW) {
-        const int r = e / TW, c = e % TW;
-        const int kx = min(tile * TW + c, a.d.M);
-        const C sf = (f == 0) ? a.tb.sfac_p[0][kx] : ((f == 1) ? sfy : a.tb.sfac_p[2][r]);
-        buf[e] = cscale(cmul(sf, xr[i]), kr[i]);
-      }
-    }
+    z_apply<T, L, TW, NT>(buf, m, xr);
     __syncthreads();
-    lds_fft<T, L, TW, TW, NT, true>(buf, a.tb.tw_z);
-    tile_store<T, L, TW, NT>(buf, sl.spec[f] + off, rstride, ncol);
+    lds_fft<T, L, TW, TW, NT, true>(buf, twl);
+    tile_store<T, L, TW, NT>(buf, (f == 0 ? s0 : (f == 1 ? s1 : s2)) + off, rstride);
   }
 }
 
@@ -422,26 +336,55 @@ __device__ __forceinline__ void lanes2d(F&& fn) {
   }
 }
 
+// Same walk over every item of the thread, in range or not, with r and k
+// clamped into range and ok telling whether the item is in range: loads are
+// issued unpredicated from a valid address (a predicated load in its own
+// branch is waited for before the next one is issued).
+template <int NR, int NK, typename F>
+__device__ __forceinline__ void lanes2d_all(F&& fn) {
+  using Ly = Lanes<NR, NK>;
+  const int kq = (int)threadIdx.x % Ly::KT;
+  const int rq = (int)threadIdx.x / Ly::KT;
+#pragma unroll
+  for (int ir = 0; ir < Ly::RI; ++ir) {
+#pragma unroll
+    for (int ik = 0; ik < Ly::KI; ++ik) {
+      const int r = rq + ir * Ly::RT;
+      const int k = kq + ik * Ly::KT;
+      const bool ok = (NR % Ly::RT == 0 || r < NR) && (NK % Ly::KT == 0 || k < NK);
+      fn(ir * Ly::KI + ik, min(r, NR - 1), min(k, NK - 1), ok);
+    }
+  }
+}
+
 // Spectra lines (M+1 complex) of NREG regions x LPB lines <-> LDS columns
-// col0 + f LPB + l, rows 0..M.
+// col0 + f LPB + l, rows 0..M.  The region loop is unrolled so that every
+// spectrum pointer is selected at compile time (a run-time index into the
+// pointer array would place it in scratch memory).
+template <typename T, int M, int LPB, int NREG> struct SpecRegs {
+  static constexpr int PER = Lanes<LPB, M + 1>::NI;
+  static constexpr int N = NREG * PER;
+};
 template <typename T, int M, int LPB, int NREG>
 __device__ __forceinline__ void x_prefetch_spectra(cplx<T>* pre, cplx<T>* const* spec, int l0, int nl, size_t px) {
   using C = cplx<T>;
-  lanes2d<NREG * LPB, M + 1>([&](int i, int r, int k) {
-    const int f = r / LPB, l = r % LPB;
-    pre[i] = (l < nl) ? spec[f][(size_t)(l0 + l) * px + k] : cmake<C>((T)0, (T)0);
-  });
+  constexpr int PER = SpecRegs<T, M, LPB, NREG>::PER;
+#pragma unroll
+  for (int f = 0; f < NREG; ++f) {
+    const C* s = spec[f];
+    lanes2d_all<LPB, M + 1>([&](int i, int l, int k, bool) {
+      const C v = gld(s + (size_t)(l0 + min(l, nl - 1)) * px + k);
+      pre[f * PER + i] = (l < nl) ? v : cmake<C>((T)0, (T)0);
+    });
+  }
 }
 template <typename T, int M, int LPB, int TWP, int NREG>
 __device__ __forceinline__ void x_commit_spectra(cplx<T>* buf, const cplx<T>* pre, int col0) {
-  lanes2d<NREG * LPB, M + 1>([&](int i, int r, int k) {
-    const int f = r / LPB, l = r % LPB;
-    buf[k * TWP + col0 + f * LPB + l] = pre[i];
-  });
+  constexpr int PER = SpecRegs<T, M, LPB, NREG>::PER;
+#pragma unroll
+  for (int f = 0; f < NREG; ++f)
+    lanes2d<LPB, M + 1>([&](int i, int l, int k) { buf[k * TWP + col0 + f * LPB + l] = pre[f * PER + i]; });
 }
-template <typename T, int M, int LPB, int NREG> struct SpecRegs {
-  static constexpr int N = Lanes<NREG * LPB, M + 1>::NI;
-};
 template <typename T, int M, int LPB, int TWP, int NREG>
 __device__ __forceinline__ void x_load_spectra(cplx<T>* buf, cplx<T>* const* spec, int col0, int l0, int nl,
                                                size_t px) {
@@ -452,10 +395,13 @@ __device__ __forceinline__ void x_load_spectra(cplx<T>* buf, cplx<T>* const* spe
 template <typename T, int M, int LPB, int TWP, int NREG>
 __device__ __forceinline__ void x_store_spectra(const cplx<T>* buf, cplx<T>* const* spec, int col0, int l0,
                                                 int nl, size_t px) {
-  lanes2d<NREG * LPB, M + 1>([&](int, int r, int k) {
-    const int f = r / LPB, l = r % LPB;
-    if (l < nl) spec[f][(size_t)(l0 + l) * px + k] = buf[k * TWP + col0 + f * LPB + l];
-  });
+#pragma unroll
+  for (int f = 0; f < NREG; ++f) {
+    cplx<T>* s = spec[f];
+    lanes2d<LPB, M + 1>([&](int, int l, int k) {
+      if (l < nl) gst(s + (size_t)(l0 + l) * px + k, buf[k * TWP + col0 + f * LPB + l]);
+    });
+  }
 }
 
 // Half spectrum X[0..M] of a length-2M real line -> Z[0..M-1] whose
@@ -511,6 +457,30 @@ __device__ __forceinline__ void r2c_post(cplx<T>* buf, const cplx<T>* __restrict
   });
 }
 
+// x-pass twiddles staged in LDS: W_M^m (m < M) of the complex length-M
+// transform followed by W_2M^k (k <= M/2) of the real <-> half-spectrum
+// pre / post processing.
+template <int M> struct XTw {
+  static constexpr int N = M + M / 2 + 1;
+  static constexpr int PER = (N + X_NT - 1) / X_NT;
+};
+template <typename T, int M>
+__device__ __forceinline__ void x_tw_prefetch(cplx<T>* tt, const Tables<T>& tb) {
+#pragma unroll
+  for (int i = 0; i < XTw<M>::PER; ++i) {
+    const int e = min((int)threadIdx.x + i * X_NT, XTw<M>::N - 1);
+    tt[i] = gld(e < M ? tb.tw_x + e : tb.rtw + (e - M));
+  }
+}
+template <typename T, int M>
+__device__ __forceinline__ void x_tw_commit(cplx<T>* twl, const cplx<T>* tt) {
+#pragma unroll
+  for (int i = 0; i < XTw<M>::PER; ++i) {
+    const int e = (int)threadIdx.x + i * X_NT;
+    if (XTw<M>::N % X_NT == 0 || e < XTw<M>::N) twl[e] = tt[i];
+  }
+}
+
 template <typename T> struct XArgs {
   const Slot<T>* slots;
   int slot0, na, slot1;   // slot ranges as in AxisArgs
@@ -522,128 +492,62 @@ template <typename T> struct XArgs {
 // X1: d+_a p (C2R of the three Z2/Y4 spectra), velocity update
 // v_a <- L^s_a (L^s_a v_a - dt/rho0 d+_a p) (Alg. 1 momentum step), R2C of v_a.
 template <typename T, int M>
-__global__ void __launch_bounds__(X_NT) k_x_velocity(XArgs<T> a) {
+__global__ void __launch_bounds__(X_NT) __attribute__((amdgpu_waves_per_eu(4))) k_x_velocity(XArgs<T> a) {
   using C = cplx<T>;
   constexpr int LPB = x_lpb_vel<T>(M);
   constexpr int NC = 3 * LPB;
   constexpr int TWP = NC;
   __shared__ C buf[(M + 1) * TWP];
+  __shared__ C twl[XTw<M>::N];
   const int l0 = blockIdx.x * LPB;
   const int nl = min(LPB, a.d.nlines - l0);
   const Slot<T> sl = a.slots[slot_of(blockIdx.y, a.slot0, a.na, a.slot1)];
   const size_t px = a.d.px;
   const int nx = a.d.nx;
-  // prefetch the velocities: in flight during the C2R transforms
-  C vv[Lanes<LPB, M>::NI][3];
-  lanes2d<LPB, M>([&](int i, int l, int n) {
+  // velocities and PML factors are prefetched: in flight during the C2R
+  // transforms.  Items of a thread share n when one row of lanes spans a line.
+  using Ly = Lanes<LPB, M>;
+  C vv[Ly::NI][3];
+  C l0f[Ly::NI];          // (Lambda^s_x at x = 2n, 2n + 1)
+  T l1f[Ly::NI], l2f[Ly::NI];
+  lanes2d_all<LPB, M>([&](int i, int l, int n, bool) {
+    const int line = l0 + min(l, nl - 1);
+    const size_t lo = (size_t)line * nx;
 #pragma unroll
-    for (int f = 0; f < 3; ++f)
-      vv[i][f] = (l < nl) ? reinterpret_cast<const C*>(sl.v[f] + (size_t)(l0 + l) * nx)[n] : cmake<C>((T)0, (T)0);
+    for (int f = 0; f < 3; ++f) vv[i][f] = gld(reinterpret_cast<const C*>(sl.v[f] + lo) + n);
+    l0f[i] = gld(reinterpret_cast<const C*>(a.tb.pml_s[0]) + n);
+    l1f[i] = gld(a.tb.pml_s[1] + line % a.d.ny);
+    l2f[i] = gld(a.tb.pml_s[2] + line / a.d.ny);
   });
-  x_load_spectra<T, M, LPB, TWP, 3>(buf, sl.spec, 0, l0, nl, px);
+  {
+    C pre[SpecRegs<T, M, LPB, 3>::N], tt[XTw<M>::PER];
+    x_prefetch_spectra<T, M, LPB, 3>(pre, sl.spec, l0, nl, px);
+    x_tw_prefetch<T, M>(tt, a.tb);
+    x_commit_spectra<T, M, LPB, TWP, 3>(buf, pre, 0);
+    x_tw_commit<T, M>(twl, tt);
+  }
   __syncthreads();
-  c2r_pre<T, M, TWP, NC>(buf, a.tb.rtw);
+  c2r_pre<T, M, TWP, NC>(buf, twl + M);
   __syncthreads();
-  lds_fft<T, M, NC, TWP, X_NT, true>(buf, a.tb.tw_x);
+  lds_fft<T, M, NC, TWP, X_NT, true>(buf, twl);
   lanes2d<LPB, M>([&](int i, int l, int n) {
     if (l >= nl) return;
     const int line = l0 + l;
-    const int yy = line % a.d.ny, zz = line / a.d.ny;
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
       const C dp = buf[n * TWP + f * LPB + l];
-      T lx, ly;
-      if (f == 0) { lx = a.tb.pml_s[0][2 * n]; ly = a.tb.pml_s[0][2 * n + 1]; }
-      else if (f == 1) { lx = ly = a.tb.pml_s[1][yy]; }
-      else { lx = ly = a.tb.pml_s[2][zz]; }
+      const T lx = f == 0 ? l0f[i].x : (f == 1 ? l1f[i] : l2f[i]);
+      const T ly = f == 0 ? l0f[i].y : (f == 1 ? l1f[i] : l2f[i]);
       const C vn = cmake<C>(lx * (lx * vv[i][f].x - a.dt_rho * dp.x), ly * (ly * vv[i][f].y - a.dt_rho * dp.y));
-      reinterpret_cast<C*>(sl.v[f] + (size_t)line * nx)[n] = vn;
+      gst(reinterpret_cast<C*>(sl.v[f] + (size_t)line * nx) + n, vn);
       buf[n * TWP + f * LPB + l] = vn;
     }
   });
   __syncthreads();
-  lds_fft<T, M, NC, TWP, X_NT, false>(buf, a.tb.tw_x);
-  r2c_post<T, M, TWP, NC>(buf, a.tb.rtw);
+  lds_fft<T, M, NC, TWP, X_NT, false>(buf, twl);
+  r2c_post<T, M, TWP, NC>(buf, twl + M);
   __syncthreads();
   x_store_spectra<T, M, LPB, TWP, 3>(buf, sl.spec, 0, l0, nl, px);
-}
-
-// Persistent X1: workgroups walk the (slot, line group) items with stride
-// gridDim.x.  The next item's spectra are loaded into registers right after
-// the current item's spectra reach LDS and its velocities right after the
-// current velocities are consumed, so HBM traffic overlaps the transforms.
-template <typename T, int M>
-__global__ void __launch_bounds__(X_NT) k_x_velocity_persist(XArgs<T> a, int nitems) {
-  using C = cplx<T>;
-  constexpr int LPB = x_lpb_vel<T>(M);
-  constexpr int NC = 3 * LPB;
-  constexpr int TWP = NC;
-  __shared__ C buf[(M + 1) * TWP];
-  const int ngroups = (a.d.nlines + LPB - 1) / LPB;
-  const size_t px = a.d.px;
-  const int nx = a.d.nx;
-  C pre[SpecRegs<T, M, LPB, 3>::N];
-  C vv[Lanes<LPB, M>::NI][3];
-  auto item_slot = [&](int it) { return a.slots[slot_of(it / ngroups, a.slot0, a.na, a.slot1)]; };
-  auto prefetch_v = [&](const Slot<T>& sl, int l0, int nl) {
-    lanes2d<LPB, M>([&](int i, int l, int n) {
-#pragma unroll
-      for (int f = 0; f < 3; ++f)
-        vv[i][f] = (l < nl) ? reinterpret_cast<const C*>(sl.v[f] + (size_t)(l0 + l) * nx)[n] : cmake<C>((T)0, (T)0);
-    });
-  };
-  int item = blockIdx.x;
-  if (item < nitems) {
-    const Slot<T> sl = item_slot(item);
-    const int l0 = (item % ngroups) * LPB;
-    const int nl = min(LPB, a.d.nlines - l0);
-    prefetch_v(sl, l0, nl);
-    x_prefetch_spectra<T, M, LPB, 3>(pre, sl.spec, l0, nl, px);
-  }
-  for (; item < nitems; item += gridDim.x) {
-    const Slot<T> sl = item_slot(item);
-    const int l0 = (item % ngroups) * LPB;
-    const int nl = min(LPB, a.d.nlines - l0);
-    const int next = item + gridDim.x;
-    const bool has_next = next < nitems;
-    x_commit_spectra<T, M, LPB, TWP, 3>(buf, pre, 0);
-    __syncthreads();
-    if (has_next) {
-      const Slot<T> sn = item_slot(next);
-      const int n0 = (next % ngroups) * LPB;
-      x_prefetch_spectra<T, M, LPB, 3>(pre, sn.spec, n0, min(LPB, a.d.nlines - n0), px);
-    }
-    c2r_pre<T, M, TWP, NC>(buf, a.tb.rtw);
-    __syncthreads();
-    lds_fft<T, M, NC, TWP, X_NT, true>(buf, a.tb.tw_x);
-    lanes2d<LPB, M>([&](int i, int l, int n) {
-      if (l >= nl) return;
-      const int line = l0 + l;
-      const int yy = line % a.d.ny, zz = line / a.d.ny;
-#pragma unroll
-      for (int f = 0; f < 3; ++f) {
-        const C dp = buf[n * TWP + f * LPB + l];
-        T lx, ly;
-        if (f == 0) { lx = a.tb.pml_s[0][2 * n]; ly = a.tb.pml_s[0][2 * n + 1]; }
-        else if (f == 1) { lx = ly = a.tb.pml_s[1][yy]; }
-        else { lx = ly = a.tb.pml_s[2][zz]; }
-        const C vn = cmake<C>(lx * (lx * vv[i][f].x - a.dt_rho * dp.x), ly * (ly * vv[i][f].y - a.dt_rho * dp.y));
-        reinterpret_cast<C*>(sl.v[f] + (size_t)line * nx)[n] = vn;
-        buf[n * TWP + f * LPB + l] = vn;
-      }
-    });
-    if (has_next) {
-      const Slot<T> sn = item_slot(next);
-      const int n0 = (next % ngroups) * LPB;
-      prefetch_v(sn, n0, min(LPB, a.d.nlines - n0));
-    }
-    __syncthreads();
-    lds_fft<T, M, NC, TWP, X_NT, false>(buf, a.tb.tw_x);
-    r2c_post<T, M, TWP, NC>(buf, a.tb.rtw);
-    __syncthreads();
-    x_store_spectra<T, M, LPB, TWP, 3>(buf, sl.spec, 0, l0, nl, px);
-    __syncthreads();
-  }
 }
 
 enum XMode { XM_FWD = 0, XM_PAIR = 1, XM_TRONLY = 2, XM_ADJONLY = 3 };
@@ -715,10 +619,12 @@ __device__ __forceinline__ int local_line(const int32_t* off, int l0, int nl, in
 // Dirichlet on dGamma), p = c0^2 sum_a rho_a written to column pcol of buf.
 // state_mode: 0 = one density step, 1 = zero state (TR start from the tape
 // only), 2 = keep the stored densities (TR start from the final forward state)
-template <typename T, int M, int LPB, int TWP, int TWPP, int KIND>
+// STAGE_TW: this call also stages the x twiddles in twl (the first call of
+// the workgroup); later calls find them there.
+template <typename T, int M, int LPB, int TWP, int TWPP, int KIND, bool STAGE_TW>
 __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx& si, const Slot<T>& sl, int b,
                                                int l0, int nl, int state_mode, int pcol, cplx<T>* buf,
-                                               cplx<T>* bufp, cplx<T>* spv, uint8_t* spm) {
+                                               cplx<T>* bufp, cplx<T>* spv, uint8_t* spm, cplx<T>* twl) {
   const bool zero_state = state_mode == 1;
   const bool no_step = state_mode != 0;
   using C = cplx<T>;
@@ -726,18 +632,32 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx
   const int nx = a.d.nx;
   const size_t px = a.d.px;
   const T* cb = a.c + (size_t)b * a.d.nfield;
-  // prefetch c0 and the split densities: in flight during the C2R transforms
+  // prefetch c0, the split densities and the PML factors: in flight during
+  // the C2R transforms
   constexpr int EB = Lanes<LPB, M>::NI;
-  C cc[EB], rr[EB][3];
-  lanes2d<LPB, M>([&](int i, int l, int n) {
-    const bool ok = l < nl;
-    const size_t lo = (size_t)(l0 + l) * nx;
-    cc[i] = ok ? reinterpret_cast<const C*>(cb + lo)[n] : cmake<C>((T)0, (T)0);
+  C cc[EB], rr[EB][3], l0f[EB];
+  T l1f[EB], l2f[EB];
+  lanes2d_all<LPB, M>([&](int i, int l, int n, bool) {
+    const int line = l0 + min(l, nl - 1);
+    const size_t lo = (size_t)line * nx;
+    cc[i] = gld(reinterpret_cast<const C*>(cb + lo) + n);
+    if (!zero_state) {
 #pragma unroll
-    for (int f = 0; f < 3; ++f)
-      rr[i][f] = (ok && !zero_state) ? reinterpret_cast<const C*>(sl.rho[f] + lo)[n] : cmake<C>((T)0, (T)0);
+      for (int f = 0; f < 3; ++f) rr[i][f] = gld(reinterpret_cast<const C*>(sl.rho[f] + lo) + n);
+    }
+    if (!no_step) {
+      l0f[i] = gld(reinterpret_cast<const C*>(a.tb.pml_n[0]) + n);
+      l1f[i] = gld(a.tb.pml_n[1] + line % a.d.ny);
+      l2f[i] = gld(a.tb.pml_n[2] + line / a.d.ny);
+    }
   });
-  if (!no_step) x_load_spectra<T, M, LPB, TWP, 3>(buf, sl.spec, 0, l0, nl, px);
+  {
+    C pre[SpecRegs<T, M, LPB, 3>::N], tt[XTw<M>::PER];
+    if (!no_step) x_prefetch_spectra<T, M, LPB, 3>(pre, sl.spec, l0, nl, px);
+    if (STAGE_TW) x_tw_prefetch<T, M>(tt, a.tb);
+    if (!no_step) x_commit_spectra<T, M, LPB, TWP, 3>(buf, pre, 0);
+    if (STAGE_TW) x_tw_commit<T, M>(twl, tt);
+  }
   for (int e = threadIdx.x; e < M * LPB; e += X_NT) {
     spv[e] = cmake<C>((T)0, (T)0);
     if (KIND == SP_DIRICHLET) { spm[2 * e] = 0; spm[2 * e + 1] = 0; }
@@ -779,16 +699,15 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx
     }
   }
   if (!no_step) {
-    c2r_pre<T, M, TWP, NC>(buf, a.tb.rtw);
+    c2r_pre<T, M, TWP, NC>(buf, twl + M);
     __syncthreads();
-    lds_fft<T, M, NC, TWP, X_NT, true>(buf, a.tb.tw_x);
+    lds_fft<T, M, NC, TWP, X_NT, true>(buf, twl);
   } else {
     __syncthreads();
   }
   lanes2d<LPB, M>([&](int i, int l, int n) {
     if (l >= nl) return;
     const int line = l0 + l;
-    const int yy = line % a.d.ny, zz = line / a.d.ny;
     const C c2 = cc[i];
     const C sv = spv[n * LPB + l];
     C sum = cmake<C>((T)0, (T)0);
@@ -802,10 +721,8 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx
         rn = rr[i][f];
       } else {
         const C dv = buf[n * TWP + f * LPB + l];
-        T lx, ly;
-        if (f == 0) { lx = a.tb.pml_n[0][2 * n]; ly = a.tb.pml_n[0][2 * n + 1]; }
-        else if (f == 1) { lx = ly = a.tb.pml_n[1][yy]; }
-        else { lx = ly = a.tb.pml_n[2][zz]; }
+        const T lx = f == 0 ? l0f[i].x : (f == 1 ? l1f[i] : l2f[i]);
+        const T ly = f == 0 ? l0f[i].y : (f == 1 ? l1f[i] : l2f[i]);
         rn = cmake<C>(lx * (lx * rr[i][f].x - a.dt_rho0 * dv.x), ly * (ly * rr[i][f].y - a.dt_rho0 * dv.y));
       }
       if (KIND == SP_DIRICHLET) {
@@ -814,7 +731,7 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx
       } else {
         rn = cadd(rn, sv);
       }
-      *rp = rn;
+      gst(rp, rn);
       sum = cadd(sum, rn);
     }
     bufp[n * TWPP + pcol + l] = cmake<C>(c2.x * c2.x * sum.x, c2.y * c2.y * sum.y);
@@ -847,6 +764,7 @@ __global__ void __launch_bounds__(X_NT) k_x_density(X2Args<T> a) {
   __shared__ C bufp[(M + 1) * TWPP];
   __shared__ C spv[M * LPB];
   __shared__ uint8_t spm[(MODE == XM_PAIR || MODE == XM_TRONLY) ? 2 * M * LPB : 1];
+  __shared__ C twl[XTw<M>::N];
   const int l0 = blockIdx.x * LPB;
   const int nl = min(LPB, a.d.nlines - l0);
   const int b = blockIdx.y;
@@ -859,7 +777,8 @@ __global__ void __launch_bounds__(X_NT) k_x_density(X2Args<T> a) {
   const StepIdx si = step_indices<T, MODE>(a);
 
   if (MODE == XM_FWD) {
-    density_update<T, M, LPB, TWP, TWPP, SP_SOURCE>(a, si, s_tr, b, l0, nl, 0, PA, buf, bufp, spv, spm);
+    density_update<T, M, LPB, TWP, TWPP, SP_SOURCE, true>(a, si, s_tr, b, l0, nl, 0, PA, buf, bufp, spv, spm,
+                                                          twl);
     // sensors f^n = M p and boundary tape g^n = p(dGamma)
     const int i0 = a.g.rec_off[l0], i1 = a.g.rec_off[l0 + nl];
     for (int i = i0 + (int)threadIdx.x; i < i1; i += X_NT) {
@@ -877,11 +796,12 @@ __global__ void __launch_bounds__(X_NT) k_x_density(X2Args<T> a) {
     }
   }
   if (MODE == XM_PAIR || MODE == XM_ADJONLY) {
-    density_update<T, M, LPB, TWP, TWPP, SP_ADJOINT>(a, si, s_adj, b, l0, nl, 0, PA, buf, bufp, spv, spm);
+    density_update<T, M, LPB, TWP, TWPP, SP_ADJOINT, true>(a, si, s_adj, b, l0, nl, 0, PA, buf, bufp, spv,
+                                                           spm, twl);
   }
   if (MODE == XM_PAIR || MODE == XM_TRONLY) {
-    density_update<T, M, LPB, TWP, TWPP, SP_DIRICHLET>(a, si, s_tr, b, l0, nl, a.tr_state_mode, PT, buf, bufp,
-                                                       spv, spm);
+    density_update<T, M, LPB, TWP, TWPP, SP_DIRICHLET, MODE == XM_TRONLY>(a, si, s_tr, b, l0, nl, a.tr_state_mode,
+                                                                          PT, buf, bufp, spv, spm, twl);
   }
   if (MODE != XM_FWD) {
     // ring update and gradient: G += 2/c0^3 p_adj (p_tr^(j) - 2 p_tr^(j+1) + p_tr^(j+2))
@@ -908,8 +828,8 @@ __global__ void __launch_bounds__(X_NT) k_x_density(X2Args<T> a) {
   }
   __syncthreads();
   // forward x-transform of the new pressure(s)
-  lds_fft<T, M, TWPP, TWPP, X_NT, false>(bufp, a.tb.tw_x);
-  r2c_post<T, M, TWPP, TWPP>(bufp, a.tb.rtw);
+  lds_fft<T, M, TWPP, TWPP, X_NT, false>(bufp, twl);
+  r2c_post<T, M, TWPP, TWPP>(bufp, twl + M);
   __syncthreads();
   if (NP == 2) {
     cplx<T>* specs[2] = {s_adj.spec[0], s_tr.spec[0]};
@@ -1010,16 +930,15 @@ __global__ void __launch_bounds__(X_NT) k_x_r2c(XArgs<T> a, const T* in, int f) 
   __shared__ C buf[(M + 1) * TWP];
   const int l0 = blockIdx.x * LPB;
   const int nl = min(LPB, a.d.nlines - l0);
-  const Slot<T> sl = a.slots[a.slot0];
   lanes2d<LPB, M>([&](int, int l, int n) {
-    buf[n * TWP + l] = (l < nl) ? reinterpret_cast<const C*>(in + (size_t)(l0 + l) * a.d.nx)[n]
+    buf[n * TWP + l] = (l < nl) ? gld(reinterpret_cast<const C*>(in + (size_t)(l0 + l) * a.d.nx) + n)
                                 : cmake<C>((T)0, (T)0);
   });
   __syncthreads();
   lds_fft<T, M, LPB, TWP, X_NT, false>(buf, a.tb.tw_x);
   r2c_post<T, M, TWP, LPB>(buf, a.tb.rtw);
   __syncthreads();
-  cplx<T>* specs[1] = {sl.spec[f]};
+  cplx<T>* specs[1] = {a.slots[a.slot0].spec[f]};
   x_store_spectra<T, M, LPB, TWP, 1>(buf, specs, 0, l0, nl, a.d.px);
 }
 
@@ -1031,15 +950,14 @@ __global__ void __launch_bounds__(X_NT) k_x_c2r(XArgs<T> a, T* out, int f) {
   __shared__ C buf[(M + 1) * TWP];
   const int l0 = blockIdx.x * LPB;
   const int nl = min(LPB, a.d.nlines - l0);
-  const Slot<T> sl = a.slots[a.slot0];
-  cplx<T>* specs[1] = {sl.spec[f]};
+  cplx<T>* specs[1] = {a.slots[a.slot0].spec[f]};
   x_load_spectra<T, M, LPB, TWP, 1>(buf, specs, 0, l0, nl, a.d.px);
   __syncthreads();
   c2r_pre<T, M, TWP, LPB>(buf, a.tb.rtw);
   __syncthreads();
   lds_fft<T, M, LPB, TWP, X_NT, true>(buf, a.tb.tw_x);
   lanes2d<LPB, M>([&](int, int l, int n) {
-    if (l < nl) reinterpret_cast<C*>(out + (size_t)(l0 + l) * a.d.nx)[n] = buf[n * TWP + l];
+    if (l < nl) gst(reinterpret_cast<C*>(out + (size_t)(l0 + l) * a.d.nx) + n, buf[n * TWP + l]);
   });
 }
 

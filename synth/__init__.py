@@ -15,5 +15,6 @@ from .configs import (  # noqa: F401
     Problem,
     make_config,
     make_small,
+    random_traces,
     CONFIG_NAMES,
 )

@@ -1,0 +1,79 @@
+"""GPU parity at the large sizes against stored FP64 oracle results.
+
+The oracle needs minutes at these sizes, so tests/golden/make_golden.py (which
+calls only oracle/ and synth/) stored its outputs, rounded to FP32.  The GPU
+runs the same seeded inputs through the C-ABI in FP32 and in the launch
+configuration bench.py times (batch 1, full grid, PML 20 for 'fullgrid').
+Tolerances: traces rel l2 <= 1e-4, misfit and gradients rel <= 1e-3.
+"""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden")
+sys.path.insert(0, GOLDEN)
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("case", ["c128", "fullgrid"])
+def test_large_case_matches_stored_oracle(case):
+    import make_golden
+    from paper_2102_00755_amd.fwi import Handle
+
+    path = os.path.join(GOLDEN, f"{case}_oracle.npz")
+    ref = np.load(path)
+    prob = make_golden.problem(case)
+    print(f"golden case {case} shape={prob.shape} nt={prob.nt}", flush=True)
+    w = oracle.rademacher(prob.enc_seed, prob.n_src)
+    assert np.array_equal(w, ref["w"])
+    h = Handle.from_problem(prob, precision=4)
+    S = torch.from_numpy(prob.src_signals())
+    wt = torch.from_numpy(w)
+    traces = h.forward(torch.from_numpy(prob.c_true), S, wt)[0].cpu().numpy()
+    assert rel(traces, ref["traces_true"]) < 1e-4
+    if "residual" in ref.files:
+        # backward of the traces from the stored residual, tape at c_eval
+        r = ref["residual"]
+        assert np.array_equal(r, make_golden.fullgrid_residual(prob))
+        h.forward(torch.from_numpy(prob.c_eval), S, wt, save_tape=True)
+        mis, grad = h.backward(torch.from_numpy(prob.c_eval), torch.from_numpy(r))
+    else:
+        mis, grad = h.gradient(torch.from_numpy(prob.c_eval), S, wt, torch.from_numpy(ref["traces_true"]))
+    D = float(ref["misfit"])
+    assert abs(float(mis[0]) - D) <= 1e-3 * D
+    g = prob.gamma.astype(bool)
+    got = grad[0].cpu().numpy()
+    assert rel(got[g], ref["grad_gamma"]) < 1e-3
+    assert np.all(got[~g] == 0)
+    h.close()
+
+
+def test_full_size_derivative_matches_oracle():
+    # the spectral derivative of eq. DisPartDevSt on the 448x448x224 grid
+    from oracle import kspace as ks
+    from paper_2102_00755_amd.fwi import Handle
+    import make_golden
+    prob = make_golden.fullgrid_problem()
+    h = Handle.from_problem(prob, precision=4)
+    sch = ks.scheme_for(prob)
+    rng = np.random.default_rng(8)
+    g = rng.standard_normal(prob.shape)
+    for axis, sign in ((0, 1), (1, -1), (2, 1)):
+        got = h.derivative(torch.from_numpy(g), axis, sign).cpu().numpy()
+        want = sch.d_plus(g, axis) if sign > 0 else sch.d_minus(g, axis)
+        assert rel(got, want) < 2e-6, (axis, sign)
+    h.close()
