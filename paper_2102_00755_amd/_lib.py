@@ -1,7 +1,9 @@
 """ctypes declarations of the C-ABI in include/fwi.h.
 
-Loads ``libfwi.so`` from this package directory.  There is no fallback: if
-the library is missing, importing the binding raises ``FwiLibraryMissing``.
+Loads ``libfwi.so`` from this package directory, or from the path in the
+environment variable ``FWI_LIBRARY`` (another build of the same sources, for
+instance one made with different tuning macros by ``build.py --out``).  There
+is no fallback: if the library is missing, loading raises ``FwiLibraryMissing``.
 """
 
 from __future__ import annotations
@@ -11,7 +13,7 @@ import os
 from ctypes import POINTER, c_char_p, c_double, c_int, c_int8, c_int32, c_int64, c_uint8, c_uint64, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libfwi.so")
+LIB_PATH = os.environ.get("FWI_LIBRARY") or os.path.join(HERE, "libfwi.so")
 
 FWI_OK = 0
 FWI_ERR_INVALID_ARG = 1

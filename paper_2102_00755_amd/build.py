@@ -6,6 +6,11 @@ disabled for device code (``-Xclang -target-feature -Xclang -packed-fp32-ops``).
 
     python -m paper_2102_00755_amd.build            # build
     python -m paper_2102_00755_amd.build --jobs 8
+    python -m paper_2102_00755_amd.build --define FWI_AXIS_TILE_BYTES=128 --out /tmp/libfwi_t128.so
+
+``--define`` sets a tuning macro of the kernels (see the top of
+csrc/kernels.h); ``--out`` writes such a variant elsewhere (load it with
+``FWI_LIBRARY=<path>``) and leaves the in-tree library alone.
 """
 
 from __future__ import annotations
@@ -37,39 +42,44 @@ CFLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
+def _compile(src: str, objdir: str, defines) -> str:
+    obj = os.path.join(objdir, os.path.basename(src) + ".o")
+    cmd = [HIPCC, *CFLAGS, *[f"-D{d}" for d in defines], "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
-    os.makedirs(OBJDIR, exist_ok=True)
+def build(jobs: int | None = None, verbose: bool = False, defines=(), out: str | None = None) -> str:
+    lib = out or LIB
+    objdir = OBJDIR if not defines and out is None else os.path.join(
+        OBJDIR, "variant_" + "_".join(d.replace("=", "-") for d in defines) if defines else "variant")
+    os.makedirs(objdir, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     if not srcs:
         raise RuntimeError("no HIP sources found")
     jobs = jobs or min(8, os.cpu_count() or 1)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda src: _compile(src, objdir, defines), srcs))
+    tmp = lib + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(f"built {LIB}")
-    return LIB
+        print(f"built {lib}")
+    return lib
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
+    ap.add_argument("--define", action="append", default=[], help="NAME=VALUE tuning macro")
+    ap.add_argument("--out", default=None, help="library path (default: in-tree libfwi.so)")
     args = ap.parse_args(argv)
-    build(args.jobs, verbose=True)
+    build(args.jobs, verbose=True, defines=args.define, out=args.out)
 
 
 if __name__ == "__main__":

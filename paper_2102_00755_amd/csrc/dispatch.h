@@ -22,10 +22,12 @@ inline bool length_supported(int L) {
 template <typename T> hipError_t launch_axis_y(int L, bool inv, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
 template <typename T> hipError_t launch_axis_zm(int L, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
 template <typename T> hipError_t launch_axis_zp(int L, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
+template <typename T> hipError_t launch_axis_ys(int L, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
 template <typename T> hipError_t launch_x_vel(int M, dim3 grid, hipStream_t st, const XArgs<T>& a);
 template <typename T> hipError_t launch_x_den(int M, int mode, dim3 grid, hipStream_t st, const X2Args<T>& a);
 template <typename T> hipError_t launch_x_r2c(int M, dim3 grid, hipStream_t st, const XArgs<T>& a, const T* in, int f);
-template <typename T> hipError_t launch_x_c2r(int M, dim3 grid, hipStream_t st, const XArgs<T>& a, T* out, int f);
+template <typename T>
+hipError_t launch_x_c2r(int M, dim3 grid, hipStream_t st, const XArgs<T>& a, T* out, int f, const cplx<T>* mult);
 
 template <typename T> inline int x_lines_per_block(int M) { return x_lpb<T>(M); }
 template <typename T> inline int x_lines_per_block_vel(int M) { return x_lpb_vel<T>(M); }

@@ -159,7 +159,7 @@ int build_geometry(const fwi_params& p, const fwi_geometry* g, Geometry& out) {
 }
 
 inline int spec_pitch(const fwi_params& p) {
-  const int tw = p.precision == 4 ? axis_tw<float>() : axis_tw<double>();
+  const int tw = p.precision == 4 ? pitch_tw<float>() : pitch_tw<double>();
   const int mh = p.nx / 2 + 1;
   return (mh + tw - 1) / tw * tw;
 }
@@ -501,7 +501,8 @@ template <typename T> struct Engine : EngineBase {
     a.d = d; a.tb = tb; a.scale = scale; a.kap_a = kap_a;
     return a;
   }
-  int ntx() const { return (d.M + 1 + axis_tw<T>() - 1) / axis_tw<T>(); }
+  // tiles per spectrum row of an axis pass
+  template <int KIND> int ntx() const { return (d.px + axis_tw<T, KIND>() - 1) / axis_tw<T, KIND>(); }
 
   // the seven passes Y3 .. Y2 + X1 of one step on nslots slots
   // algorithmic bytes of one half spectrum / one real field
@@ -510,8 +511,9 @@ template <typename T> struct Engine : EngineBase {
 
   // Y3 .. Y2 of one step; half_only stops after the velocity pass X1
   int step_spectral(int slot0, int na, int slot1, int nslots, hipStream_t st, bool half_only = false) {
-    const dim3 gy(ntx() * d.nz, nslots * 1), gy3(ntx() * d.nz, nslots * 3);
-    const dim3 gz(ntx() * d.ny, nslots), gz3(ntx() * d.ny, nslots * 3);
+    const dim3 gy(ntx<AK_Y>() * d.nz, nslots * 1), gy2(ntx<AK_Y>() * d.nz, nslots * 2),
+        gy3(ntx<AK_Y>() * d.nz, nslots * 3);
+    const dim3 gz(ntx<AK_ZPLUS>() * d.ny, nslots), gz3(ntx<AK_ZMINUS>() * d.ny, nslots * 3);
     const double S = sbytes(), F = fbytes(), ns = nslots;
     hipEvent_t ev;
     ev = timer.begin(st);
@@ -519,10 +521,10 @@ template <typename T> struct Engine : EngineBase {
     timer.end(ev, FWI_PASS_Y_FWD, 2 * ns * S, st);
     ev = timer.begin(st);
     FWI_HIP(launch_axis_zp<T>(d.nz, gz, st, axis_args(slot0, na, slot1, 1, 0)));             // Z2
-    timer.end(ev, FWI_PASS_Z_PLUS, 4 * ns * S, st);
+    timer.end(ev, FWI_PASS_Z_PLUS, 3 * ns * S, st);
     ev = timer.begin(st);
-    FWI_HIP(launch_axis_y<T>(d.ny, true, gy3, st, axis_args(slot0, na, slot1, 3, 0)));       // Y4
-    timer.end(ev, FWI_PASS_Y_INV, 6 * ns * S, st);
+    FWI_HIP(launch_axis_ys<T>(d.ny, gy2, st, axis_args(slot0, na, slot1, 2, 0)));            // Y4
+    timer.end(ev, FWI_PASS_Y_INV, 5 * ns * S, st);
     XArgs<T> xa;
     xa.slots = slot_table; xa.slot0 = slot0; xa.na = na; xa.slot1 = slot1;
     xa.d = d; xa.tb = tb; xa.dt_rho = (T)(p.dt / p.rho0);
@@ -830,11 +832,17 @@ template <typename T> struct Engine : EngineBase {
     const dim3 gx((d.nlines + lpb - 1) / lpb, 1);
     const int f = sign > 0 ? 0 : axis;
     FWI_HIP(launch_x_r2c<T>(d.M, gx, st, xa, (const T*)in, f));
-    FWI_HIP(launch_axis_y<T>(d.ny, false, dim3(ntx() * d.nz, 1), st, axis_args(s, 1, s, 1, f)));
-    if (sign > 0) FWI_HIP(launch_axis_zp<T>(d.nz, dim3(ntx() * d.ny, 1), st, axis_args(s, 1, s, 1, 0)));
-    else FWI_HIP(launch_axis_zm<T>(d.nz, dim3(ntx() * d.ny, 1), st, axis_args(s, 1, s, 1, axis)));
-    FWI_HIP(launch_axis_y<T>(d.ny, true, dim3(ntx() * d.nz, 1), st, axis_args(s, 1, s, 1, axis)));
-    FWI_HIP(launch_x_c2r<T>(d.M, gx, st, xa, (T*)out, axis));
+    FWI_HIP(launch_axis_y<T>(d.ny, false, dim3(ntx<AK_Y>() * d.nz, 1), st, axis_args(s, 1, s, 1, f)));
+    if (sign > 0) {
+      // Z2 and the split inverse y pass of the time step; the x shift factor
+      // of d+_x is applied by the C2R
+      FWI_HIP(launch_axis_zp<T>(d.nz, dim3(ntx<AK_ZPLUS>() * d.ny, 1), st, axis_args(s, 1, s, 1, 0)));
+      FWI_HIP(launch_axis_ys<T>(d.ny, dim3(ntx<AK_Y>() * d.nz, 2), st, axis_args(s, 1, s, 2, 0)));
+    } else {
+      FWI_HIP(launch_axis_zm<T>(d.nz, dim3(ntx<AK_ZMINUS>() * d.ny, 1), st, axis_args(s, 1, s, 1, axis)));
+      FWI_HIP(launch_axis_y<T>(d.ny, true, dim3(ntx<AK_Y>() * d.nz, 1), st, axis_args(s, 1, s, 1, axis)));
+    }
+    FWI_HIP(launch_x_c2r<T>(d.M, gx, st, xa, (T*)out, axis, (sign > 0 && axis == 0) ? tb.sfac_p[0] : nullptr));
     return FWI_OK;
   }
 };

@@ -3,7 +3,7 @@
 // Field layout: [nz][ny][nx] reals, x fastest.  Spectra: [nz][ny][px]
 // complex, where px >= nx/2 + 1 is the row pitch of the half spectrum along
 // x (real-to-complex along x, complex along y and z).  px is a multiple of
-// the axis-pass tile width so that every tile row starts on a 128-byte line.
+// 128 bytes, so that every axis-pass tile row starts on a cache line.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -24,14 +24,53 @@
 namespace fwi {
 
 // ----------------------------------------------------------------------------
-// launch geometry
+// launch geometry (tuning macros: set with build.py --define)
 // ----------------------------------------------------------------------------
-// axis-pass tile width: 64-byte row segments (8 FP32 / 4 FP64 complex); measured
-// faster than 128-byte segments because twice as many tiles fit in LDS per CU
-template <typename T> constexpr int axis_tw() { return 64 / (int)(2 * sizeof(T)); }
+// FWI_Y_TILE_BYTES     row segment of a y-pass tile in bytes (64 or 128)
+// FWI_ZM_TILE_BYTES    the same for the Z1 pass (z_minus)
+// FWI_ZP_TILE_BYTES    the same for the Z2 pass (z_plus: one field in, three out)
+// FWI_AXIS_MAX_NT      largest axis-pass workgroup (one thread per 8 elements)
+// FWI_PITCH_BYTES      the spectrum row pitch px is a multiple of this
+// FWI_XVEL_LDS_BUDGET  x-lines per X1 workgroup = budget / (M sizeof(T)), odd
+// FWI_XDEN_LDS_BUDGET  the same for X2
+// Measured on the 448x448x224 FP32 step (per-pass HIP-event times): 128-byte
+// tiles on a 128-byte pitch are fastest overall; a 64-byte pitch makes half
+// of the 128-byte tile rows straddle two cache lines, a 256-byte pitch slows
+// the y and z passes (row stride 2 KiB).
+#ifndef FWI_Y_TILE_BYTES
+#define FWI_Y_TILE_BYTES 128
+#endif
+#ifndef FWI_ZM_TILE_BYTES
+#define FWI_ZM_TILE_BYTES 128
+#endif
+#ifndef FWI_ZP_TILE_BYTES
+#define FWI_ZP_TILE_BYTES 128
+#endif
+#ifndef FWI_AXIS_MAX_NT
+#define FWI_AXIS_MAX_NT 512
+#endif
+#ifndef FWI_XVEL_LDS_BUDGET
+#define FWI_XVEL_LDS_BUDGET 5120
+#endif
+#ifndef FWI_XDEN_LDS_BUDGET
+#define FWI_XDEN_LDS_BUDGET 3072
+#endif
+enum AxisKind { AK_Y = 0, AK_ZMINUS = 1, AK_ZPLUS = 2 };
+// axis-pass tile width in complex elements
+template <typename T, int KIND> constexpr int axis_tw() {
+  return (KIND == AK_Y ? FWI_Y_TILE_BYTES : (KIND == AK_ZMINUS ? FWI_ZM_TILE_BYTES : FWI_ZP_TILE_BYTES)) /
+         (int)(2 * sizeof(T));
+}
+// The spectrum row pitch px is a multiple of FWI_PITCH_BYTES; a tile at the
+// end of a row may extend past px and then holds only its first columns in
+// memory.
+#ifndef FWI_PITCH_BYTES
+#define FWI_PITCH_BYTES 128
+#endif
+template <typename T> constexpr int pitch_tw() { return FWI_PITCH_BYTES / (int)(2 * sizeof(T)); }
 constexpr int axis_nt(int L, int TW) {
   int n = L * TW / 8;
-  n = n < 64 ? 64 : (n > 256 ? 256 : n);
+  n = n < 64 ? 64 : (n > FWI_AXIS_MAX_NT ? FWI_AXIS_MAX_NT : n);
   return (n + 63) / 64 * 64;
 }
 // x-lines per workgroup of the x passes.  LDS regions hold the lines as
@@ -46,8 +85,8 @@ template <typename T> constexpr int odd_lpb(int budget, int M) {
   if ((l & 1) == 0) l -= 1;
   return l;
 }
-template <typename T> constexpr int x_lpb_vel(int M) { return odd_lpb<T>(5120, M); }
-template <typename T> constexpr int x_lpb_den(int M) { return odd_lpb<T>(3072, M); }
+template <typename T> constexpr int x_lpb_vel(int M) { return odd_lpb<T>(FWI_XVEL_LDS_BUDGET, M); }
+template <typename T> constexpr int x_lpb_den(int M) { return odd_lpb<T>(FWI_XDEN_LDS_BUDGET, M); }
 template <typename T> constexpr int x_lpb(int M) { return odd_lpb<T>(4096, M); }
 constexpr int X_NT = 256;
 
@@ -90,19 +129,21 @@ __device__ __forceinline__ int slot_of(int i, int slot0, int na, int slot1) {
   return i < na ? slot0 + i : slot1 + (i - na);
 }
 
-// Whole tiles are moved: the spectrum pitch px is a multiple of TW, so the
-// padding columns of the last tile (kx > M) are in bounds.  They are
-// transformed with the valid columns (columns never mix) and never read by
-// the x passes.  Loads are unpredicated so that a thread's loads are all in
-// flight before the first wait, and full 64-byte row segments are written.
+// Tiles are moved whole within the row pitch: the padding columns of the last
+// tile (kx > M) are in bounds, transformed with the valid columns (columns
+// never mix) and never read by the x passes.  ncol = min(TW, px - kx0) is the
+// number of tile columns that exist in memory (less than TW only for a
+// 128-byte tile at the end of a row).  Loads are unpredicated, from clamped
+// columns, so that a thread's loads are all in flight before the first wait;
+// stores are predicated on c < ncol and otherwise write full row segments.
 template <typename T, int L, int TW, int NT>
-__device__ __forceinline__ void tile_prefetch(cplx<T>* tmp, const cplx<T>* g, size_t rstride) {
+__device__ __forceinline__ void tile_prefetch(cplx<T>* tmp, const cplx<T>* g, size_t rstride, int ncol) {
   constexpr int E = L * TW;
   constexpr int EPT = (E + NT - 1) / NT;
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int e = min((int)threadIdx.x + i * NT, E - 1);
-    tmp[i] = gld(g + (size_t)(e / TW) * rstride + e % TW);
+    tmp[i] = gld(g + (size_t)(e / TW) * rstride + min(e % TW, ncol - 1));
   }
 }
 template <typename T, int L, int TW, int NT>
@@ -116,13 +157,13 @@ __device__ __forceinline__ void tile_commit(cplx<T>* buf, const cplx<T>* tmp) {
   }
 }
 template <typename T, int L, int TW, int NT>
-__device__ __forceinline__ void tile_store(const cplx<T>* buf, cplx<T>* g, size_t rstride) {
+__device__ __forceinline__ void tile_store(const cplx<T>* buf, cplx<T>* g, size_t rstride, int ncol) {
   constexpr int E = L * TW;
   constexpr int EPT = (E + NT - 1) / NT;
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int e = (int)threadIdx.x + i * NT;
-    if (E % NT == 0 || e < E) gst(g + (size_t)(e / TW) * rstride + e % TW, buf[e]);
+    if ((E % NT == 0 || e < E) && e % TW < ncol) gst(g + (size_t)(e / TW) * rstride + e % TW, buf[e]);
   }
 }
 
@@ -148,10 +189,10 @@ __device__ __forceinline__ void tw_commit(cplx<T>* twl, const cplx<T>* tt) {
 
 // Tile and twiddles into LDS (loads of both in flight together).
 template <typename T, int L, int TW, int NT>
-__device__ __forceinline__ void tile_load(cplx<T>* buf, const cplx<T>* g, size_t rstride, cplx<T>* twl,
+__device__ __forceinline__ void tile_load(cplx<T>* buf, const cplx<T>* g, size_t rstride, int ncol, cplx<T>* twl,
                                           const cplx<T>* tw) {
   cplx<T> tmp[(L * TW + NT - 1) / NT], tt[TwRegs<L, NT>::N_PER];
-  tile_prefetch<T, L, TW, NT>(tmp, g, rstride);
+  tile_prefetch<T, L, TW, NT>(tmp, g, rstride, ncol);
   tw_prefetch<T, L, NT>(tt, tw);
   tile_commit<T, L, TW, NT>(buf, tmp);
   tw_commit<T, L, NT>(twl, tt);
@@ -159,24 +200,25 @@ __device__ __forceinline__ void tile_load(cplx<T>* buf, const cplx<T>* g, size_t
 
 // Y pass: in-place FFT along y of nf fields per slot.  L == ny.
 template <typename T, int L, bool INV>
-__global__ void __launch_bounds__(axis_nt(L, axis_tw<T>()))
+__global__ void __launch_bounds__(axis_nt(L, axis_tw<T, AK_Y>()))
 k_axis_y(AxisArgs<T> a) {
   using C = cplx<T>;
-  constexpr int TW = axis_tw<T>();
+  constexpr int TW = axis_tw<T, AK_Y>();
   constexpr int NT = axis_nt(L, TW);
   __shared__ C buf[L * TW];
   __shared__ C twl[L];
-  const int ntx = a.d.px / TW;   // tiles per row: px is a multiple of TW
+  const int ntx = (a.d.px + TW - 1) / TW;   // tiles per spectrum row
   const int tile = blockIdx.x % ntx;
   const int z = blockIdx.x / ntx;
   const int s = slot_of(blockIdx.y / a.nf, a.slot0, a.na, a.slot1);
   const int f = a.f0 + blockIdx.y % a.nf;
   const size_t px = a.d.px;
   C* g = a.slots[s].spec[f] + (size_t)z * L * px + (size_t)tile * TW;
-  tile_load<T, L, TW, NT>(buf, g, px, twl, a.tb.tw_y);
+  const int ncol = min(TW, (int)px - tile * TW);
+  tile_load<T, L, TW, NT>(buf, g, px, ncol, twl, a.tb.tw_y);
   __syncthreads();
   lds_fft<T, L, TW, TW, NT, INV>(buf, twl);
-  tile_store<T, L, TW, NT>(buf, g, px);
+  tile_store<T, L, TW, NT>(buf, g, px, ncol);
 }
 
 // k-space multipliers of the elements a thread owns in a z tile: thread t
@@ -226,15 +268,15 @@ __device__ __forceinline__ void z_apply(cplx<T>* buf, const cplx<T>* m, const cp
 // Z pass of the velocity divergence terms: field f -> F_z^-1 m-_f F_z field f
 // (eq. DisPartDevSt with the minus shift).  L == nz.
 template <typename T, int L>
-__global__ void __launch_bounds__(axis_nt(L, axis_tw<T>()))
+__global__ void __launch_bounds__(axis_nt(L, axis_tw<T, AK_ZMINUS>()))
 k_axis_z_minus(AxisArgs<T> a) {
   using C = cplx<T>;
-  constexpr int TW = axis_tw<T>();
+  constexpr int TW = axis_tw<T, AK_ZMINUS>();
   constexpr int NT = axis_nt(L, TW);
   constexpr int EPT = (L * TW + NT - 1) / NT;
   __shared__ C buf[L * TW];
   __shared__ C twl[L];
-  const int ntx = a.d.px / TW;   // tiles per row: px is a multiple of TW
+  const int ntx = (a.d.px + TW - 1) / TW;   // tiles per spectrum row
   const int tile = blockIdx.x % ntx;
   const int y = blockIdx.x / ntx;
   const int s = slot_of(blockIdx.y / a.nf, a.slot0, a.na, a.slot1);
@@ -242,61 +284,120 @@ k_axis_z_minus(AxisArgs<T> a) {
   const size_t px = a.d.px;
   const size_t rstride = (size_t)a.d.ny * px;
   C* g = a.slots[s].spec[f] + (size_t)y * px + (size_t)tile * TW;
+  const int ncol = min(TW, (int)px - tile * TW);
   const int kx = min(tile * TW + (int)threadIdx.x % TW, a.d.M);
   T kap[EPT];
   C m[EPT];
   z_kappa<T, L, TW, NT>(a, kx, y, kap);
   z_mult<T, L, TW, NT>(a, a.tb.sfac_m, f, kx, y, kap, m);
-  tile_load<T, L, TW, NT>(buf, g, rstride, twl, a.tb.tw_z);
+  tile_load<T, L, TW, NT>(buf, g, rstride, ncol, twl, a.tb.tw_z);
   __syncthreads();
   lds_fft<T, L, TW, TW, NT, false>(buf, twl);
   z_apply<T, L, TW, NT>(buf, m, nullptr);
   __syncthreads();
   lds_fft<T, L, TW, TW, NT, true>(buf, twl);
-  tile_store<T, L, TW, NT>(buf, g, rstride);
+  tile_store<T, L, TW, NT>(buf, g, rstride, ncol);
 }
 
-// Z pass of the pressure gradient: field 0 (p_hat) -> fields 0,1,2 =
-// F_z^-1 m+_a F_z p_hat for a = x, y, z.  L == nz.
+// Z pass of the pressure gradient, field 0 (p_hat) -> two fields:
+//   field 0: Q = F_z^-1 kappa F_z p_hat                (for d+_x and d+_y)
+//   field 2: R = F_z^-1 kappa i k_z e^{+i k_z dz/2} F_z p_hat   (d+_z)
+// The shift factors i k_a e^{+i k_a da/2} of x and y are separable and are
+// applied later, in the y pass (y) and the x pass (x), where those wave
+// numbers are at hand: one spectrum less is written here and read there.
+// L == nz.
 template <typename T, int L>
-__global__ void __launch_bounds__(axis_nt(L, axis_tw<T>()))
+__global__ void __launch_bounds__(axis_nt(L, axis_tw<T, AK_ZPLUS>()))
 k_axis_z_plus(AxisArgs<T> a) {
   using C = cplx<T>;
-  constexpr int TW = axis_tw<T>();
+  constexpr int TW = axis_tw<T, AK_ZPLUS>();
   constexpr int NT = axis_nt(L, TW);
   constexpr int EPT = (L * TW + NT - 1) / NT;
   __shared__ C buf[L * TW];
   __shared__ C twl[L];
-  const int ntx = a.d.px / TW;   // tiles per row: px is a multiple of TW
+  const int ntx = (a.d.px + TW - 1) / TW;   // tiles per spectrum row
   const int tile = blockIdx.x % ntx;
   const int y = blockIdx.x / ntx;
   const int s = slot_of(blockIdx.y, a.slot0, a.na, a.slot1);
   const size_t px = a.d.px;
   const size_t rstride = (size_t)a.d.ny * px;
   const size_t off = (size_t)y * px + (size_t)tile * TW;
+  const int ncol = min(TW, (int)px - tile * TW);
   const int kx = min(tile * TW + (int)threadIdx.x % TW, a.d.M);
   C* const s0 = a.slots[s].spec[0];
-  C* const s1 = a.slots[s].spec[1];
   C* const s2 = a.slots[s].spec[2];
   T kap[EPT];
+  C m[EPT];
   z_kappa<T, L, TW, NT>(a, kx, y, kap);
-  tile_load<T, L, TW, NT>(buf, s0 + off, rstride, twl, a.tb.tw_z);
+  z_mult<T, L, TW, NT>(a, a.tb.sfac_p, 2, kx, y, kap, m);
+  tile_load<T, L, TW, NT>(buf, s0 + off, rstride, ncol, twl, a.tb.tw_z);
   __syncthreads();
   lds_fft<T, L, TW, TW, NT, false>(buf, twl);
-  C xr[EPT], m[EPT];
+  C xr[EPT];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int e = (int)threadIdx.x + i * NT;
     if ((L * TW) % NT == 0 || e < L * TW) xr[i] = buf[e];
   }
+  __syncthreads();
 #pragma unroll
-  for (int f = 0; f < 3; ++f) {
-    z_mult<T, L, TW, NT>(a, a.tb.sfac_p, f, kx, y, kap, m);
+  for (int i = 0; i < EPT; ++i) {
+    const int e = (int)threadIdx.x + i * NT;
+    if ((L * TW) % NT == 0 || e < L * TW) buf[e] = cscale(xr[i], kap[i]);
+  }
+  __syncthreads();
+  lds_fft<T, L, TW, TW, NT, true>(buf, twl);
+  tile_store<T, L, TW, NT>(buf, s0 + off, rstride, ncol);
+  __syncthreads();
+  z_apply<T, L, TW, NT>(buf, m, xr);
+  __syncthreads();
+  lds_fft<T, L, TW, TW, NT, true>(buf, twl);
+  tile_store<T, L, TW, NT>(buf, s2 + off, rstride, ncol);
+}
+
+// Inverse y pass after Z2: per slot, part 0 reads Q (field 0) and writes
+// F_y^-1 Q to field 0 and F_y^-1 (i k_y e^{+i k_y dy/2} Q) to field 1; part 1
+// transforms R (field 2) in place.  grid.y = 2 x slots.  L == ny.
+template <typename T, int L>
+__global__ void __launch_bounds__(axis_nt(L, axis_tw<T, AK_Y>()))
+k_axis_y_split(AxisArgs<T> a) {
+  using C = cplx<T>;
+  constexpr int TW = axis_tw<T, AK_Y>();
+  constexpr int NT = axis_nt(L, TW);
+  constexpr int E = L * TW;
+  constexpr int EPT = (E + NT - 1) / NT;
+  __shared__ C buf[L * TW];
+  __shared__ C twl[L];
+  __shared__ C sfl[L];
+  const int ntx = (a.d.px + TW - 1) / TW;   // tiles per spectrum row
+  const int tile = blockIdx.x % ntx;
+  const int z = blockIdx.x / ntx;
+  const int part = blockIdx.y & 1;
+  const int s = slot_of(blockIdx.y >> 1, a.slot0, a.na, a.slot1);
+  const size_t px = a.d.px;
+  const size_t off = (size_t)z * L * px + (size_t)tile * TW;
+  const int ncol = min(TW, (int)px - tile * TW);
+  C* const g = a.slots[s].spec[part == 0 ? 0 : 2] + off;
+  C tmp[EPT], tt[TwRegs<L, NT>::N_PER], ts[TwRegs<L, NT>::N_PER];
+  tile_prefetch<T, L, TW, NT>(tmp, g, px, ncol);
+  tw_prefetch<T, L, NT>(tt, a.tb.tw_y);
+  if (part == 0) tw_prefetch<T, L, NT>(ts, a.tb.sfac_p[1]);
+  tile_commit<T, L, TW, NT>(buf, tmp);
+  tw_commit<T, L, NT>(twl, tt);
+  if (part == 0) tw_commit<T, L, NT>(sfl, ts);
+  __syncthreads();
+  lds_fft<T, L, TW, TW, NT, true>(buf, twl);
+  tile_store<T, L, TW, NT>(buf, g, px, ncol);
+  if (part == 0) {
     __syncthreads();
-    z_apply<T, L, TW, NT>(buf, m, xr);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = (int)threadIdx.x + i * NT;
+      if (E % NT == 0 || e < E) buf[e] = cmul(sfl[e / TW], tmp[i]);
+    }
     __syncthreads();
     lds_fft<T, L, TW, TW, NT, true>(buf, twl);
-    tile_store<T, L, TW, NT>(buf, (f == 0 ? s0 : (f == 1 ? s1 : s2)) + off, rstride);
+    tile_store<T, L, TW, NT>(buf, a.slots[s].spec[1] + off, px, ncol);
   }
 }
 
@@ -520,9 +621,14 @@ __global__ void __launch_bounds__(X_NT) __attribute__((amdgpu_waves_per_eu(4))) 
     l2f[i] = gld(a.tb.pml_s[2] + line / a.d.ny);
   });
   {
-    C pre[SpecRegs<T, M, LPB, 3>::N], tt[XTw<M>::PER];
+    // field 0 holds F_y^-1 Q (Z2): its x shift factor i k_x e^{+i k_x dx/2}
+    // is applied here, in the x wave-number domain
+    C pre[SpecRegs<T, M, LPB, 3>::N], tt[XTw<M>::PER], sx[Lanes<LPB, M + 1>::NI];
     x_prefetch_spectra<T, M, LPB, 3>(pre, sl.spec, l0, nl, px);
     x_tw_prefetch<T, M>(tt, a.tb);
+    lanes2d_all<LPB, M + 1>([&](int i, int, int k, bool) { sx[i] = gld(a.tb.sfac_p[0] + k); });
+#pragma unroll
+    for (int i = 0; i < Lanes<LPB, M + 1>::NI; ++i) pre[i] = cmul(sx[i], pre[i]);
     x_commit_spectra<T, M, LPB, TWP, 3>(buf, pre, 0);
     x_tw_commit<T, M>(twl, tt);
   }
@@ -942,8 +1048,9 @@ __global__ void __launch_bounds__(X_NT) k_x_r2c(XArgs<T> a, const T* in, int f) 
   x_store_spectra<T, M, LPB, TWP, 1>(buf, specs, 0, l0, nl, a.d.px);
 }
 
+// mult (may be null): per-kx factor applied before the inverse transform
 template <typename T, int M>
-__global__ void __launch_bounds__(X_NT) k_x_c2r(XArgs<T> a, T* out, int f) {
+__global__ void __launch_bounds__(X_NT) k_x_c2r(XArgs<T> a, T* out, int f, const cplx<T>* mult) {
   using C = cplx<T>;
   constexpr int LPB = x_lpb<T>(M);
   constexpr int TWP = LPB;
@@ -953,6 +1060,10 @@ __global__ void __launch_bounds__(X_NT) k_x_c2r(XArgs<T> a, T* out, int f) {
   cplx<T>* specs[1] = {a.slots[a.slot0].spec[f]};
   x_load_spectra<T, M, LPB, TWP, 1>(buf, specs, 0, l0, nl, a.d.px);
   __syncthreads();
+  if (mult) {
+    lanes2d<LPB, M + 1>([&](int, int l, int k) { buf[k * TWP + l] = cmul(gld(mult + k), buf[k * TWP + l]); });
+    __syncthreads();
+  }
   c2r_pre<T, M, TWP, LPB>(buf, a.tb.rtw);
   __syncthreads();
   lds_fft<T, M, LPB, TWP, X_NT, true>(buf, a.tb.tw_x);
