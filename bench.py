@@ -35,7 +35,33 @@ KERNEL_SYMBOLS = {
     "x_vel": "k_x_velocity<float, {m}>",
     "x_den_fwd": "k_x_density<float, {m}, 0>",
     "x_den_pair": "k_x_density<float, {m}, 1>",
+    "y_split": "k_axis_y_split<float, {ny}>",
 }
+
+
+def measured_traffic(kernel: str, bytes_per_launch: float):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (profiles/*_pmc.txt): its measured/algorithmic ratio times this
+    run's algorithmic bytes per launch.  None when no summary covers the
+    kernel or when the library sources changed since the counters were taken
+    (sha256 over csrc/)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2102_00755_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    sha = h.hexdigest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_pmc.txt"))):
+        kv = {}
+        with open(path) as fh:
+            for line in fh:
+                if ": " in line and not line.startswith(" "):
+                    k, v = line.rstrip("\n").split(": ", 1)
+                    kv[k] = v
+        if kv.get("kernel") == kernel and kv.get("source_sha256") == sha:
+            return round(float(kv["traffic_over_algorithmic"]) * bytes_per_launch, 1)
+    return None
 
 
 def parse():
@@ -148,7 +174,8 @@ def main():
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": round(d["GB/s"] / PEAK_HBM_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(KERNEL_SYMBOLS[dom].format(nx=nx, ny=ny, nz=nz, m=nx // 2),
+                                        d["bytes_per_launch"]),
             "kernel": KERNEL_SYMBOLS[dom].format(nx=nx, ny=ny, nz=nz, m=nx // 2),
             "avg_ms": round(d["avg_ms"], 4),
             "bytes_per_launch": d["bytes_per_launch"],

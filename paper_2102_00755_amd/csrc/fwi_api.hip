@@ -524,7 +524,7 @@ template <typename T> struct Engine : EngineBase {
     timer.end(ev, FWI_PASS_Z_PLUS, 3 * ns * S, st);
     ev = timer.begin(st);
     FWI_HIP(launch_axis_ys<T>(d.ny, gy2, st, axis_args(slot0, na, slot1, 2, 0)));            // Y4
-    timer.end(ev, FWI_PASS_Y_INV, 5 * ns * S, st);
+    timer.end(ev, FWI_PASS_Y_SPLIT, 5 * ns * S, st);
     XArgs<T> xa;
     xa.slots = slot_table; xa.slot0 = slot0; xa.na = na; xa.slot1 = slot1;
     xa.d = d; xa.tb = tb; xa.dt_rho = (T)(p.dt / p.rho0);
