@@ -496,11 +496,20 @@ __device__ __forceinline__ void x_load_spectra(cplx<T>* buf, cplx<T>* const* spe
 template <typename T, int M, int LPB, int TWP, int NREG>
 __device__ __forceinline__ void x_store_spectra(const cplx<T>* buf, cplx<T>* const* spec, int col0, int l0,
                                                 int nl, size_t px) {
+  // Whole rows up to the pitch, zeros past k = M: every store covers full
+  // 128-byte lines.  A partial last line per row (1800 of 1920 bytes at
+  // nx = 448) made the x passes 9 % slower: the memory side merges partial
+  // lines by read-modify-write.  The zero padding stays zero through the y and
+  // z passes (columns never mix).
+  constexpr int PT = pitch_tw<T>();
+  constexpr int NK = (M + 1 + PT - 1) / PT * PT;
 #pragma unroll
   for (int f = 0; f < NREG; ++f) {
     cplx<T>* s = spec[f];
-    lanes2d<LPB, M + 1>([&](int, int l, int k) {
-      if (l < nl) gst(s + (size_t)(l0 + l) * px + k, buf[k * TWP + col0 + f * LPB + l]);
+    lanes2d<LPB, NK>([&](int, int l, int k) {
+      if (l < nl)
+        gst(s + (size_t)(l0 + l) * px + k,
+            (NK == M + 1 || k <= M) ? buf[k * TWP + col0 + f * LPB + l] : cmake<cplx<T>>((T)0, (T)0));
     });
   }
 }
