@@ -162,6 +162,25 @@ int fwi_backward(fwi_handle* h, int32_t B, const void* c, const void* residual,
 int fwi_derivative(fwi_handle* h, const void* in, void* out, int32_t axis, int32_t sign,
                    fwi_stream_t stream);
 
+/* Launch tuning of a handle: the row segment, in bytes, of the tiles of the
+ * y passes, of the z pass of d- (Z1) and of the z pass of d+ (Z2); each 64 or
+ * 128.  The tile width changes only which threads compute which columns, not
+ * the arithmetic: results are bit-identical across tunings.  New handles
+ * start from the build's defaults (measured fastest at 448x448x224);
+ * paper_2102_00755_amd.autotune measures the alternatives per grid. */
+typedef struct {
+  int32_t y_tile_bytes;
+  int32_t zm_tile_bytes;
+  int32_t zp_tile_bytes;
+} fwi_tuning;
+
+/* Read the handle's tuning into *out. */
+int fwi_get_tuning(const fwi_handle* h, fwi_tuning* out);
+
+/* Set the tuning used by subsequent calls on the handle (not by calls already
+ * enqueued).  FWI_ERR_INVALID_ARG (tuning unchanged) for other values. */
+int fwi_set_tuning(fwi_handle* h, const fwi_tuning* t);
+
 /* Pass kinds of one time step, for fwi_timing_* (one kernel symbol each). */
 enum {
   FWI_PASS_Y_FWD = 0,    /* forward y-FFT                                     */

@@ -34,7 +34,8 @@ SUPPORTED_LENGTHS = (8, 12, 16, 24, 32, 40, 48, 56, 64, 80, 96, 112, 128, 160, 2
 # every symbol declared in include/fwi.h
 EXPORTED = (
     "fwi_create", "fwi_destroy", "fwi_workspace_bytes", "fwi_rademacher", "fwi_delays", "fwi_forward",
-    "fwi_gradient", "fwi_backward", "fwi_derivative", "fwi_timing_enable", "fwi_timing_read",
+    "fwi_gradient", "fwi_backward", "fwi_derivative", "fwi_get_tuning", "fwi_set_tuning",
+    "fwi_timing_enable", "fwi_timing_read",
     "fwi_status_string", "fwi_last_error",
 )
 
@@ -63,6 +64,10 @@ class FwiGeometry(ctypes.Structure):
         ("n_rec", c_int32), ("rec_ijk", POINTER(c_int32)),
         ("gamma_mask", POINTER(c_uint8)), ("boundary_mask", POINTER(c_uint8)),
     ]
+
+
+class FwiTuning(ctypes.Structure):
+    _fields_ = [("y_tile_bytes", c_int32), ("zm_tile_bytes", c_int32), ("zp_tile_bytes", c_int32)]
 
 
 _lib = None
@@ -98,6 +103,10 @@ def load(path: str = LIB_PATH):
     lib.fwi_backward.restype = c_int
     lib.fwi_derivative.argtypes = [h, c_void_p, c_void_p, c_int32, c_int32, c_void_p]
     lib.fwi_derivative.restype = c_int
+    lib.fwi_get_tuning.argtypes = [h, POINTER(FwiTuning)]
+    lib.fwi_get_tuning.restype = c_int
+    lib.fwi_set_tuning.argtypes = [h, POINTER(FwiTuning)]
+    lib.fwi_set_tuning.restype = c_int
     lib.fwi_timing_enable.argtypes = [h, c_int32]
     lib.fwi_timing_enable.restype = c_int
     lib.fwi_timing_read.argtypes = [h, c_int32, POINTER(c_int64), POINTER(c_double), POINTER(c_double)]

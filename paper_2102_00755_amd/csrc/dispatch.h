@@ -18,11 +18,13 @@ inline bool length_supported(int L) {
   }
 }
 
-// Each returns hipErrorInvalidValue for an unsupported length.
-template <typename T> hipError_t launch_axis_y(int L, bool inv, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
-template <typename T> hipError_t launch_axis_zm(int L, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
-template <typename T> hipError_t launch_axis_zp(int L, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
-template <typename T> hipError_t launch_axis_ys(int L, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
+// Each returns hipErrorInvalidValue for an unsupported length or tile width
+// (tb = row segment of an axis-pass tile in bytes: 64 or 128).
+template <typename T>
+hipError_t launch_axis_y(int L, bool inv, int tb, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
+template <typename T> hipError_t launch_axis_zm(int L, int tb, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
+template <typename T> hipError_t launch_axis_zp(int L, int tb, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
+template <typename T> hipError_t launch_axis_ys(int L, int tb, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
 template <typename T> hipError_t launch_x_vel(int M, dim3 grid, hipStream_t st, const XArgs<T>& a);
 template <typename T> hipError_t launch_x_den(int M, int mode, dim3 grid, hipStream_t st, const X2Args<T>& a);
 template <typename T> hipError_t launch_x_r2c(int M, dim3 grid, hipStream_t st, const XArgs<T>& a, const T* in, int f);

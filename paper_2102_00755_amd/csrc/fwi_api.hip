@@ -296,6 +296,8 @@ struct EngineBase {
                        hipStream_t st) = 0;
   virtual int derivative(const void* in, void* out, int axis, int sign, hipStream_t st) = 0;
   PassTimer timer;
+  // axis-pass tile row segments in bytes (run-time tuning, fwi_set_tuning)
+  int tile_bytes[3] = {FWI_Y_TILE_BYTES, FWI_ZM_TILE_BYTES, FWI_ZP_TILE_BYTES};
 };
 
 template <typename T> struct Engine : EngineBase {
@@ -502,7 +504,11 @@ template <typename T> struct Engine : EngineBase {
     return a;
   }
   // tiles per spectrum row of an axis pass
-  template <int KIND> int ntx() const { return (d.px + axis_tw<T, KIND>() - 1) / axis_tw<T, KIND>(); }
+  // tiles per spectrum row of an axis pass of kind k (AxisKind)
+  int ntx(int k) const {
+    const int tw = tile_bytes[k] / (int)sizeof(C);
+    return (d.px + tw - 1) / tw;
+  }
 
   // the seven passes Y3 .. Y2 + X1 of one step on nslots slots
   // algorithmic bytes of one half spectrum / one real field
@@ -511,19 +517,20 @@ template <typename T> struct Engine : EngineBase {
 
   // Y3 .. Y2 of one step; half_only stops after the velocity pass X1
   int step_spectral(int slot0, int na, int slot1, int nslots, hipStream_t st, bool half_only = false) {
-    const dim3 gy(ntx<AK_Y>() * d.nz, nslots * 1), gy2(ntx<AK_Y>() * d.nz, nslots * 2),
-        gy3(ntx<AK_Y>() * d.nz, nslots * 3);
-    const dim3 gz(ntx<AK_ZPLUS>() * d.ny, nslots), gz3(ntx<AK_ZMINUS>() * d.ny, nslots * 3);
+    const int ty = tile_bytes[AK_Y], tzm = tile_bytes[AK_ZMINUS], tzp = tile_bytes[AK_ZPLUS];
+    const dim3 gy(ntx(AK_Y) * d.nz, nslots * 1), gy2(ntx(AK_Y) * d.nz, nslots * 2),
+        gy3(ntx(AK_Y) * d.nz, nslots * 3);
+    const dim3 gz(ntx(AK_ZPLUS) * d.ny, nslots), gz3(ntx(AK_ZMINUS) * d.ny, nslots * 3);
     const double S = sbytes(), F = fbytes(), ns = nslots;
     hipEvent_t ev;
     ev = timer.begin(st);
-    FWI_HIP(launch_axis_y<T>(d.ny, false, gy, st, axis_args(slot0, na, slot1, 1, 0)));       // Y3
+    FWI_HIP(launch_axis_y<T>(d.ny, false, ty, gy, st, axis_args(slot0, na, slot1, 1, 0)));   // Y3
     timer.end(ev, FWI_PASS_Y_FWD, 2 * ns * S, st);
     ev = timer.begin(st);
-    FWI_HIP(launch_axis_zp<T>(d.nz, gz, st, axis_args(slot0, na, slot1, 1, 0)));             // Z2
+    FWI_HIP(launch_axis_zp<T>(d.nz, tzp, gz, st, axis_args(slot0, na, slot1, 1, 0)));        // Z2
     timer.end(ev, FWI_PASS_Z_PLUS, 3 * ns * S, st);
     ev = timer.begin(st);
-    FWI_HIP(launch_axis_ys<T>(d.ny, gy2, st, axis_args(slot0, na, slot1, 2, 0)));            // Y4
+    FWI_HIP(launch_axis_ys<T>(d.ny, ty, gy2, st, axis_args(slot0, na, slot1, 2, 0)));        // Y4
     timer.end(ev, FWI_PASS_Y_SPLIT, 5 * ns * S, st);
     XArgs<T> xa;
     xa.slots = slot_table; xa.slot0 = slot0; xa.na = na; xa.slot1 = slot1;
@@ -534,13 +541,13 @@ template <typename T> struct Engine : EngineBase {
     timer.end(ev, FWI_PASS_X_VEL, ns * (6 * S + 6 * F), st);
     if (half_only) return FWI_OK;
     ev = timer.begin(st);
-    FWI_HIP(launch_axis_y<T>(d.ny, false, gy3, st, axis_args(slot0, na, slot1, 3, 0)));      // Y1
+    FWI_HIP(launch_axis_y<T>(d.ny, false, ty, gy3, st, axis_args(slot0, na, slot1, 3, 0)));  // Y1
     timer.end(ev, FWI_PASS_Y_FWD, 6 * ns * S, st);
     ev = timer.begin(st);
-    FWI_HIP(launch_axis_zm<T>(d.nz, gz3, st, axis_args(slot0, na, slot1, 3, 0)));            // Z1
+    FWI_HIP(launch_axis_zm<T>(d.nz, tzm, gz3, st, axis_args(slot0, na, slot1, 3, 0)));       // Z1
     timer.end(ev, FWI_PASS_Z_MINUS, 6 * ns * S, st);
     ev = timer.begin(st);
-    FWI_HIP(launch_axis_y<T>(d.ny, true, gy3, st, axis_args(slot0, na, slot1, 3, 0)));       // Y2
+    FWI_HIP(launch_axis_y<T>(d.ny, true, ty, gy3, st, axis_args(slot0, na, slot1, 3, 0)));   // Y2
     timer.end(ev, FWI_PASS_Y_INV, 6 * ns * S, st);
     return FWI_OK;
   }
@@ -832,15 +839,16 @@ template <typename T> struct Engine : EngineBase {
     const dim3 gx((d.nlines + lpb - 1) / lpb, 1);
     const int f = sign > 0 ? 0 : axis;
     FWI_HIP(launch_x_r2c<T>(d.M, gx, st, xa, (const T*)in, f));
-    FWI_HIP(launch_axis_y<T>(d.ny, false, dim3(ntx<AK_Y>() * d.nz, 1), st, axis_args(s, 1, s, 1, f)));
+    const int ty = tile_bytes[AK_Y], tzm = tile_bytes[AK_ZMINUS], tzp = tile_bytes[AK_ZPLUS];
+    FWI_HIP(launch_axis_y<T>(d.ny, false, ty, dim3(ntx(AK_Y) * d.nz, 1), st, axis_args(s, 1, s, 1, f)));
     if (sign > 0) {
       // Z2 and the split inverse y pass of the time step; the x shift factor
       // of d+_x is applied by the C2R
-      FWI_HIP(launch_axis_zp<T>(d.nz, dim3(ntx<AK_ZPLUS>() * d.ny, 1), st, axis_args(s, 1, s, 1, 0)));
-      FWI_HIP(launch_axis_ys<T>(d.ny, dim3(ntx<AK_Y>() * d.nz, 2), st, axis_args(s, 1, s, 2, 0)));
+      FWI_HIP(launch_axis_zp<T>(d.nz, tzp, dim3(ntx(AK_ZPLUS) * d.ny, 1), st, axis_args(s, 1, s, 1, 0)));
+      FWI_HIP(launch_axis_ys<T>(d.ny, ty, dim3(ntx(AK_Y) * d.nz, 2), st, axis_args(s, 1, s, 2, 0)));
     } else {
-      FWI_HIP(launch_axis_zm<T>(d.nz, dim3(ntx<AK_ZMINUS>() * d.ny, 1), st, axis_args(s, 1, s, 1, axis)));
-      FWI_HIP(launch_axis_y<T>(d.ny, true, dim3(ntx<AK_Y>() * d.nz, 1), st, axis_args(s, 1, s, 1, axis)));
+      FWI_HIP(launch_axis_zm<T>(d.nz, tzm, dim3(ntx(AK_ZMINUS) * d.ny, 1), st, axis_args(s, 1, s, 1, axis)));
+      FWI_HIP(launch_axis_y<T>(d.ny, true, ty, dim3(ntx(AK_Y) * d.nz, 1), st, axis_args(s, 1, s, 1, axis)));
     }
     FWI_HIP(launch_x_c2r<T>(d.M, gx, st, xa, (T*)out, axis, (sign > 0 && axis == 0) ? tb.sfac_p[0] : nullptr));
     return FWI_OK;
@@ -942,6 +950,23 @@ int fwi_backward(fwi_handle* h, int32_t B, const void* c, const void* residual, 
 int fwi_derivative(fwi_handle* h, const void* in, void* out, int32_t axis, int32_t sign, fwi_stream_t stream) {
   if (!h) return fail(FWI_ERR_INVALID_ARG, "handle is NULL");
   return h->eng->derivative(in, out, axis, sign, (hipStream_t)stream);
+}
+
+int fwi_get_tuning(const fwi_handle* h, fwi_tuning* out) {
+  if (!h || !out) return fail(FWI_ERR_INVALID_ARG, "bad arguments");
+  out->y_tile_bytes = h->eng->tile_bytes[AK_Y];
+  out->zm_tile_bytes = h->eng->tile_bytes[AK_ZMINUS];
+  out->zp_tile_bytes = h->eng->tile_bytes[AK_ZPLUS];
+  return FWI_OK;
+}
+
+int fwi_set_tuning(fwi_handle* h, const fwi_tuning* t) {
+  if (!h || !t) return fail(FWI_ERR_INVALID_ARG, "bad arguments");
+  const int v[3] = {t->y_tile_bytes, t->zm_tile_bytes, t->zp_tile_bytes};
+  for (int k = 0; k < 3; ++k)
+    if (v[k] != 64 && v[k] != 128) return fail(FWI_ERR_INVALID_ARG, "tile bytes must be 64 or 128");
+  for (int k = 0; k < 3; ++k) h->eng->tile_bytes[k] = v[k];
+  return FWI_OK;
 }
 
 int fwi_timing_enable(fwi_handle* h, int32_t every) {

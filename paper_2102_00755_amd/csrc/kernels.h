@@ -26,9 +26,10 @@ namespace fwi {
 // ----------------------------------------------------------------------------
 // launch geometry (tuning macros: set with build.py --define)
 // ----------------------------------------------------------------------------
-// FWI_Y_TILE_BYTES     row segment of a y-pass tile in bytes (64 or 128)
+// FWI_Y_TILE_BYTES     default row segment of a y-pass tile in bytes (64 or 128;
+//                      per handle at run time: fwi_set_tuning)
 // FWI_ZM_TILE_BYTES    the same for the Z1 pass (z_minus)
-// FWI_ZP_TILE_BYTES    the same for the Z2 pass (z_plus: one field in, three out)
+// FWI_ZP_TILE_BYTES    the same for the Z2 pass (z_plus: one field in, two out)
 // FWI_AXIS_MAX_NT      largest axis-pass workgroup (one thread per 8 elements)
 // FWI_PITCH_BYTES      the spectrum row pitch px is a multiple of this
 // FWI_XVEL_LDS_BUDGET  x-lines per X1 workgroup = budget / (M sizeof(T)), odd
@@ -56,11 +57,8 @@ namespace fwi {
 #define FWI_XDEN_LDS_BUDGET 3072
 #endif
 enum AxisKind { AK_Y = 0, AK_ZMINUS = 1, AK_ZPLUS = 2 };
-// axis-pass tile width in complex elements
-template <typename T, int KIND> constexpr int axis_tw() {
-  return (KIND == AK_Y ? FWI_Y_TILE_BYTES : (KIND == AK_ZMINUS ? FWI_ZM_TILE_BYTES : FWI_ZP_TILE_BYTES)) /
-         (int)(2 * sizeof(T));
-}
+// axis-pass tile width in complex elements for a row segment of TB bytes
+template <typename T, int TB> constexpr int tile_tw() { return TB / (int)(2 * sizeof(T)); }
 // The spectrum row pitch px is a multiple of FWI_PITCH_BYTES; a tile at the
 // end of a row may extend past px and then holds only its first columns in
 // memory.
@@ -199,11 +197,11 @@ __device__ __forceinline__ void tile_load(cplx<T>* buf, const cplx<T>* g, size_t
 }
 
 // Y pass: in-place FFT along y of nf fields per slot.  L == ny.
-template <typename T, int L, bool INV>
-__global__ void __launch_bounds__(axis_nt(L, axis_tw<T, AK_Y>()))
+template <typename T, int L, bool INV, int TB>
+__global__ void __launch_bounds__(axis_nt(L, tile_tw<T, TB>()))
 k_axis_y(AxisArgs<T> a) {
   using C = cplx<T>;
-  constexpr int TW = axis_tw<T, AK_Y>();
+  constexpr int TW = tile_tw<T, TB>();
   constexpr int NT = axis_nt(L, TW);
   __shared__ C buf[L * TW];
   __shared__ C twl[L];
@@ -267,11 +265,11 @@ __device__ __forceinline__ void z_apply(cplx<T>* buf, const cplx<T>* m, const cp
 
 // Z pass of the velocity divergence terms: field f -> F_z^-1 m-_f F_z field f
 // (eq. DisPartDevSt with the minus shift).  L == nz.
-template <typename T, int L>
-__global__ void __launch_bounds__(axis_nt(L, axis_tw<T, AK_ZMINUS>()))
+template <typename T, int L, int TB>
+__global__ void __launch_bounds__(axis_nt(L, tile_tw<T, TB>()))
 k_axis_z_minus(AxisArgs<T> a) {
   using C = cplx<T>;
-  constexpr int TW = axis_tw<T, AK_ZMINUS>();
+  constexpr int TW = tile_tw<T, TB>();
   constexpr int NT = axis_nt(L, TW);
   constexpr int EPT = (L * TW + NT - 1) / NT;
   __shared__ C buf[L * TW];
@@ -306,11 +304,11 @@ k_axis_z_minus(AxisArgs<T> a) {
 // applied later, in the y pass (y) and the x pass (x), where those wave
 // numbers are at hand: one spectrum less is written here and read there.
 // L == nz.
-template <typename T, int L>
-__global__ void __launch_bounds__(axis_nt(L, axis_tw<T, AK_ZPLUS>()))
+template <typename T, int L, int TB>
+__global__ void __launch_bounds__(axis_nt(L, tile_tw<T, TB>()))
 k_axis_z_plus(AxisArgs<T> a) {
   using C = cplx<T>;
-  constexpr int TW = axis_tw<T, AK_ZPLUS>();
+  constexpr int TW = tile_tw<T, TB>();
   constexpr int NT = axis_nt(L, TW);
   constexpr int EPT = (L * TW + NT - 1) / NT;
   __shared__ C buf[L * TW];
@@ -358,11 +356,11 @@ k_axis_z_plus(AxisArgs<T> a) {
 // Inverse y pass after Z2: per slot, part 0 reads Q (field 0) and writes
 // F_y^-1 Q to field 0 and F_y^-1 (i k_y e^{+i k_y dy/2} Q) to field 1; part 1
 // transforms R (field 2) in place.  grid.y = 2 x slots.  L == ny.
-template <typename T, int L>
-__global__ void __launch_bounds__(axis_nt(L, axis_tw<T, AK_Y>()))
+template <typename T, int L, int TB>
+__global__ void __launch_bounds__(axis_nt(L, tile_tw<T, TB>()))
 k_axis_y_split(AxisArgs<T> a) {
   using C = cplx<T>;
-  constexpr int TW = axis_tw<T, AK_Y>();
+  constexpr int TW = tile_tw<T, TB>();
   constexpr int NT = axis_nt(L, TW);
   constexpr int E = L * TW;
   constexpr int EPT = (E + NT - 1) / NT;

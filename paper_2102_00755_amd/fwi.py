@@ -117,6 +117,10 @@ class Handle:
                  src_ijk, rec_ijk, gamma, boundary, precision=4, batch=1, device=0):
         self._lib = L.load()
         self._h = ctypes.c_void_p(None)
+        # constructor arguments (the autotuner builds a short-horizon twin)
+        self.kwargs = dict(shape=shape, dx=dx, dt=dt, nt=nt, c_ref=c_ref, c_min=c_min, c_max=c_max, rho0=rho0,
+                           pml=pml, pml_alpha=pml_alpha, src_ijk=src_ijk, rec_ijk=rec_ijk, gamma=gamma,
+                           boundary=boundary, precision=precision)
         self.shape = tuple(int(s) for s in shape)
         self.nt = int(nt)
         self.precision = int(precision)
@@ -222,6 +226,20 @@ class Handle:
         return out
 
     # ------------------------------------------------------------------
+    @property
+    def tuning(self) -> dict:
+        """Launch tuning: {'y_tile_bytes', 'zm_tile_bytes', 'zp_tile_bytes'} (64 or 128)."""
+        t = L.FwiTuning()
+        _check(self._lib.fwi_get_tuning(self._h, ctypes.byref(t)), "fwi_get_tuning")
+        return {"y_tile_bytes": t.y_tile_bytes, "zm_tile_bytes": t.zm_tile_bytes, "zp_tile_bytes": t.zp_tile_bytes}
+
+    @tuning.setter
+    def tuning(self, value: dict) -> None:
+        cur = self.tuning
+        cur.update(value)
+        t = L.FwiTuning(int(cur["y_tile_bytes"]), int(cur["zm_tile_bytes"]), int(cur["zp_tile_bytes"]))
+        _check(self._lib.fwi_set_tuning(self._h, ctypes.byref(t)), "fwi_set_tuning")
+
     def timing_enable(self, every: int) -> None:
         """Sample every `every`-th time step's pass launches with HIP events."""
         _check(self._lib.fwi_timing_enable(self._h, int(every)), "fwi_timing_enable")

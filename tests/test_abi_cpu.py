@@ -82,3 +82,26 @@ def test_delayed_signals_shift():
     out = delayed_signals(S, [0, 3], 8)
     assert np.array_equal(out[:6, 0], S[:, 0]) and np.all(out[6:, 0] == 0)
     assert np.all(out[:3, 1] == 0) and np.array_equal(out[3:8, 1], S[:5, 1])
+
+
+def test_set_tuning_rejects_null_handle_and_bad_values():
+    L, lib = _lib()
+    t = L.FwiTuning(128, 128, 128)
+    assert lib.fwi_set_tuning(None, ctypes.byref(t)) == L.FWI_ERR_INVALID_ARG
+    assert lib.fwi_get_tuning(None, ctypes.byref(t)) == L.FWI_ERR_INVALID_ARG
+
+
+def test_autotune_choice_and_cache(tmp_path):
+    from paper_2102_00755_amd import autotune
+    per = {64: {"y_fwd": 1.0, "y_inv": 1.0, "y_split": 1.0, "z_minus": 2.0, "z_plus": 1.0},
+           128: {"y_fwd": 0.9, "y_inv": 0.9, "y_split": 1.0, "z_minus": 2.5, "z_plus": 0.5}}
+    assert autotune.choose(per) == {"y_tile_bytes": 128, "zm_tile_bytes": 64, "zp_tile_bytes": 128}
+    path = str(tmp_path / "sub" / "tuning.json")
+    assert autotune.load_cache(path) == {}
+    key = autotune.cache_key("AMD Instinct MI355X", 4, (224, 448, 448), 1)
+    assert key == "AMD Instinct MI355X|fp32|224x448x448|B1"
+    autotune.save_cache({key: {"y_tile_bytes": 128}}, path)
+    assert autotune.load_cache(path) == {key: {"y_tile_bytes": 128}}
+    with open(path, "w") as f:
+        f.write("not json")
+    assert autotune.load_cache(path) == {}

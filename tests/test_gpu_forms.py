@@ -153,3 +153,38 @@ def test_serving_mix_equals_alone():
             m, g = h.gradient(c, s, w, obs)
             assert torch.equal(g.cpu(), out[1].cpu()) and torch.equal(m.cpu(), out[0].cpu())
         h.close()
+
+
+def test_tuning_is_bit_identical_and_autotune_caches(tmp_path):
+    # tile widths change only the thread mapping: traces and gradient must be
+    # bitwise equal for every tuning; the autotuner stores and reuses a choice
+    from paper_2102_00755_amd import autotune
+    from paper_2102_00755_amd.fwi import FwiError, Handle, rademacher
+    prob = make_small(shape=(24, 40, 64), nt=24, precision=4)
+    h = Handle.from_problem(prob)
+    S = torch.from_numpy(prob.src_signals())
+    w = torch.from_numpy(rademacher(prob.enc_seed, prob.n_src))
+    c_true, c_eval = torch.from_numpy(prob.c_true), torch.from_numpy(prob.c_eval)
+    ref = None
+    for tb in [(128, 128, 128), (64, 64, 64), (64, 128, 64), (128, 64, 128)]:
+        h.tuning = dict(zip(("y_tile_bytes", "zm_tile_bytes", "zp_tile_bytes"), tb))
+        assert tuple(h.tuning.values()) == tb
+        print("tuning", tb, flush=True)
+        obs = h.forward(c_true, S, w)
+        mis, g = h.gradient(c_eval, S, w, obs[0])
+        got = (obs.cpu(), mis.cpu(), g.cpu())
+        if ref is None:
+            ref = got
+        else:
+            assert all(torch.equal(a, b) for a, b in zip(got, ref)), tb
+    with pytest.raises(FwiError):
+        h.tuning = {"y_tile_bytes": 96}
+    assert tuple(h.tuning.values()) == (128, 64, 128)
+    cache = str(tmp_path / "tuning.json")
+    choice = autotune.apply(h, cache=cache, steps=4)
+    assert set(choice.values()) <= {64, 128} and h.tuning == choice
+    data = autotune.load_cache(cache)
+    assert len(data) == 1 and "measured_ms_per_launch" in next(iter(data.values()))
+    h.tuning = {"y_tile_bytes": 64, "zm_tile_bytes": 64, "zp_tile_bytes": 64}
+    assert autotune.apply(h, cache=cache) == choice and h.tuning == choice
+    h.close()
