@@ -67,13 +67,16 @@ def measured_traffic(kernel: str, bytes_per_launch: float):
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2, help="timed TR gradients")
+    ap.add_argument("--steps", type=int, default=4, help="timed TR gradients")
     ap.add_argument("--warmup", type=int, default=1, help="untimed TR gradients")
     ap.add_argument("--config", default="full", help="synth config name (default: the full-size workload)")
     ap.add_argument("--nt", type=int, default=None, help="override the number of time steps")
     ap.add_argument("--timing-every", type=int, default=16, help="sample pass launches every k steps")
     ap.add_argument("--cpu-nt", type=int, default=2, help="time steps of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile-bytes", type=int, nargs=3, metavar=("Y", "ZM", "ZP"), default=None,
+                    help="axis-pass tile bytes (fwi_set_tuning) instead of the library defaults")
+    ap.add_argument("--autotune", action="store_true", help="apply the autotuner's cached or measured choice")
     return ap.parse_args()
 
 
@@ -125,13 +128,22 @@ def main():
     prob = make_config(args.config, nt=args.nt)
     nz, ny, nx = prob.shape
     h = Handle.from_problem(prob, batch=1, precision=4)
+    if args.tile_bytes:
+        h.tuning = dict(zip(("y_tile_bytes", "zm_tile_bytes", "zp_tile_bytes"), args.tile_bytes))
+    if args.autotune:
+        from paper_2102_00755_amd import autotune
+        autotune.apply(h)
     dev = h.device
     w = torch.from_numpy(rademacher(prob.enc_seed, prob.n_src)).to(dev)
     S = torch.from_numpy(prob.src_signals()).to(dev, torch.float32)
     c_eval = torch.from_numpy(prob.c_eval).to(dev, torch.float32)
     c_true = torch.from_numpy(prob.c_true).to(dev, torch.float32)
-    obs = h.forward(c_true, S, w)            # synthetic observed data (untimed)
+    obs = h.forward(c_true, S, w)            # synthetic observed data (also the forward warm-up)
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h.forward(c_true, S, w)                  # forward-only throughput (one simulation)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
     grad = torch.empty((1, nz, ny, nx), device=dev, dtype=torch.float32)
     for _ in range(args.warmup):
         h.gradient(c_eval, S, w, obs, out=grad)
@@ -209,6 +221,9 @@ def main():
                      for k, v in per_pass.items()},
         "misfit": misfit,
         "grad_finite": gfinite,
+        "forward_Mcell_steps_per_s": round(cells * prob.nt / t_fwd / 1e6, 1),
+        "gradients_per_hour": round(3600.0 * args.steps / total, 1),
+        "tuning": h.tuning,
     }
     h.close()
     del obs, grad, c_eval, c_true, S
