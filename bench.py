@@ -28,14 +28,14 @@ METRIC = "Mcell-steps/s of TR-gradient at 448x448x224 FP32; p50/p99 solve latenc
 PEAK_HBM_GBS = 8000.0
 
 KERNEL_SYMBOLS = {
-    "y_fwd": "k_axis_y<float, {ny}, false>",
-    "y_inv": "k_axis_y<float, {ny}, true>",
-    "z_plus": "k_axis_z_plus<float, {nz}>",
-    "z_minus": "k_axis_z_minus<float, {nz}>",
+    "y_fwd": "k_axis_y<float, {ny}, false, {ty}>",
+    "y_inv": "k_axis_y<float, {ny}, true, {ty}>",
+    "z_plus": "k_axis_z_plus<float, {nz}, {tzp}>",
+    "z_minus": "k_axis_z_minus<float, {nz}, {tzm}>",
     "x_vel": "k_x_velocity<float, {m}>",
     "x_den_fwd": "k_x_density<float, {m}, 0>",
     "x_den_pair": "k_x_density<float, {m}, 1>",
-    "y_split": "k_axis_y_split<float, {ny}>",
+    "y_split": "k_axis_y_vel<float, {ny}, {ty}>",
 }
 
 
@@ -177,6 +177,8 @@ def main():
             per_pass[name] = {"launches_sampled": n, "avg_ms": ms / n, "GB/s": by / (ms * 1e-3) / 1e9,
                               "bytes_per_launch": by / n}
     dom = max(per_pass, key=lambda k: per_pass[k]["avg_ms"] * passes[k][0]) if per_pass else None
+    tn = h.tuning
+    tiles = dict(ty=tn["y_tile_bytes"], tzm=tn["zm_tile_bytes"], tzp=tn["zp_tile_bytes"])
     roof = None
     if dom:
         d = per_pass[dom]
@@ -186,9 +188,9 @@ def main():
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": round(d["GB/s"] / PEAK_HBM_GBS, 4),
-            "traffic": measured_traffic(KERNEL_SYMBOLS[dom].format(nx=nx, ny=ny, nz=nz, m=nx // 2),
+            "traffic": measured_traffic(KERNEL_SYMBOLS[dom].format(nx=nx, ny=ny, nz=nz, m=nx // 2, **tiles),
                                         d["bytes_per_launch"]),
-            "kernel": KERNEL_SYMBOLS[dom].format(nx=nx, ny=ny, nz=nz, m=nx // 2),
+            "kernel": KERNEL_SYMBOLS[dom].format(nx=nx, ny=ny, nz=nz, m=nx // 2, **tiles),
             "avg_ms": round(d["avg_ms"], 4),
             "bytes_per_launch": d["bytes_per_launch"],
         }

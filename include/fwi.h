@@ -187,10 +187,10 @@ enum {
   FWI_PASS_Y_INV = 1,    /* inverse y-FFT                                     */
   FWI_PASS_Z_PLUS = 2,   /* z-FFT, k-space multiply for d+ (1 -> 2 fields)    */
   FWI_PASS_Z_MINUS = 3,  /* z-FFT, k-space multiply for d- (3 -> 3 fields)    */
-  FWI_PASS_X_VEL = 4,    /* C2R, velocity update, R2C                         */
+  FWI_PASS_X_VEL = 4,    /* C2R, v_x update, R2C                              */
   FWI_PASS_X_DEN_FWD = 5,  /* C2R, density/EOS/sources/sensors/tape, R2C       */
   FWI_PASS_X_DEN_PAIR = 6, /* adjoint + TR density passes with gradient        */
-  FWI_PASS_Y_SPLIT = 7,  /* inverse y-FFT after Z2 (2 -> 3 fields, y shift)   */
+  FWI_PASS_Y_SPLIT = 7,  /* inverse y-FFT after Z2 with the v_y, v_z update    */
   FWI_PASS_COUNT = 8
 };
 

@@ -25,6 +25,8 @@ hipError_t launch_axis_y(int L, bool inv, int tb, dim3 grid, hipStream_t st, con
 template <typename T> hipError_t launch_axis_zm(int L, int tb, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
 template <typename T> hipError_t launch_axis_zp(int L, int tb, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
 template <typename T> hipError_t launch_axis_ys(int L, int tb, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
+template <typename T>
+hipError_t launch_axis_yv(int L, int part, int tb, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
 template <typename T> hipError_t launch_x_vel(int M, dim3 grid, hipStream_t st, const XArgs<T>& a);
 template <typename T> hipError_t launch_x_den(int M, int mode, dim3 grid, hipStream_t st, const X2Args<T>& a);
 template <typename T> hipError_t launch_x_r2c(int M, dim3 grid, hipStream_t st, const XArgs<T>& a, const T* in, int f);

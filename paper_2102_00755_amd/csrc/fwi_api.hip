@@ -169,6 +169,8 @@ size_t align256(size_t n) { return (n + 255) / 256 * 256; }
 struct Layout {
   size_t slots_bytes = 0;    // 2*batch slots
   size_t slot_bytes = 0;
+  // offsets inside a slot: [v_x | V_y | V_z] [rho_x rho_y rho_z] [spec0 spec1 spec2]
+  size_t vy_off = 0, vz_off = 0, vel_bytes = 0, rho_off = 0, spec_off = 0;
   size_t tape_bytes = 0;
   size_t traces_bytes = 0;   // internal traces
   size_t adj_bytes = 0;
@@ -185,7 +187,12 @@ Layout make_layout(const fwi_params& p, const Geometry& g) {
   const size_t rs = p.precision;
   const size_t nfield = (size_t)p.nx * p.ny * p.nz;
   const size_t nspec = (size_t)spec_pitch(p) * p.ny * p.nz;
-  L.slot_bytes = align256(6 * nfield * rs) + align256(3 * nspec * 2 * rs);
+  L.vy_off = align256(nfield * rs);
+  L.vz_off = L.vy_off + align256(nspec * 2 * rs);
+  L.vel_bytes = L.vz_off + align256(nspec * 2 * rs);
+  L.rho_off = L.vel_bytes;
+  L.spec_off = L.rho_off + align256(3 * nfield * rs);
+  L.slot_bytes = L.spec_off + align256(3 * nspec * 2 * rs);
   L.slots_bytes = 2 * (size_t)p.batch * L.slot_bytes;
   L.tape_bytes = align256((size_t)p.batch * p.nt * std::max(g.n_bnd, 1) * rs);
   L.traces_bytes = align256((size_t)p.batch * p.nt * std::max(g.n_rec, 1) * rs);
@@ -368,17 +375,18 @@ template <typename T> struct Engine : EngineBase {
     partial = (double*)mem_partial.p;
     flag = (int*)mem_flag.p;
     step_counter = flag + 16;
-    // slots: [v0 v1 v2 rho0 rho1 rho2 | spec0 spec1 spec2], 2*batch of them
+    // slots: [v_x | V_y | V_z | rho_x rho_y rho_z | spec0 spec1 spec2], 2*batch of
+    // them; v_x is a real field, V_y and V_z are x spectra (rows of px complex)
     slots_host.resize(2 * p.batch);
     char* base = (char*)mem_slots.p;
     for (int s = 0; s < 2 * p.batch; ++s) {
       char* sb = base + (size_t)s * lay.slot_bytes;
-      T* f = (T*)sb;
-      for (int a = 0; a < 3; ++a) {
-        slots_host[s].v[a] = f + (size_t)a * d.nfield;
-        slots_host[s].rho[a] = f + (size_t)(3 + a) * d.nfield;
-      }
-      C* sp = (C*)(sb + align256(6 * (size_t)d.nfield * sizeof(T)));
+      slots_host[s].v[0] = (T*)sb;
+      slots_host[s].v[1] = (T*)(sb + lay.vy_off);
+      slots_host[s].v[2] = (T*)(sb + lay.vz_off);
+      T* r = (T*)(sb + lay.rho_off);
+      for (int a = 0; a < 3; ++a) slots_host[s].rho[a] = r + (size_t)a * d.nfield;
+      C* sp = (C*)(sb + lay.spec_off);
       for (int a = 0; a < 3; ++a) slots_host[s].spec[a] = sp + (size_t)a * d.nspec;
     }
     slot_table = (Slot<T>*)mem_slot_table.p;
@@ -501,25 +509,24 @@ template <typename T> struct Engine : EngineBase {
     AxisArgs<T> a;
     a.slots = slot_table; a.slot0 = slot0; a.na = na; a.slot1 = slot1; a.nf = nf; a.f0 = f0;
     a.d = d; a.tb = tb; a.scale = scale; a.kap_a = kap_a;
+    a.vcoef = (T)((double)p.nx * p.dt / p.rho0);
     return a;
   }
-  // tiles per spectrum row of an axis pass
   // tiles per spectrum row of an axis pass of kind k (AxisKind)
   int ntx(int k) const {
     const int tw = tile_bytes[k] / (int)sizeof(C);
     return (d.px + tw - 1) / tw;
   }
 
-  // the seven passes Y3 .. Y2 + X1 of one step on nslots slots
   // algorithmic bytes of one half spectrum / one real field
   double sbytes() const { return (double)(d.M + 1) * d.ny * d.nz * sizeof(C); }
   double fbytes() const { return (double)d.nfield * sizeof(T); }
 
-  // Y3 .. Y2 of one step; half_only stops after the velocity pass X1
+  // Y3 .. Y2 of one step (seven passes; X2 follows); half_only stops after the
+  // velocity passes (Y4 with v_y, v_z and X1 with v_x)
   int step_spectral(int slot0, int na, int slot1, int nslots, hipStream_t st, bool half_only = false) {
     const int ty = tile_bytes[AK_Y], tzm = tile_bytes[AK_ZMINUS], tzp = tile_bytes[AK_ZPLUS];
-    const dim3 gy(ntx(AK_Y) * d.nz, nslots * 1), gy2(ntx(AK_Y) * d.nz, nslots * 2),
-        gy3(ntx(AK_Y) * d.nz, nslots * 3);
+    const dim3 gy(ntx(AK_Y) * d.nz, nslots * 1), gy3(ntx(AK_Y) * d.nz, nslots * 3);
     const dim3 gz(ntx(AK_ZPLUS) * d.ny, nslots), gz3(ntx(AK_ZMINUS) * d.ny, nslots * 3);
     const double S = sbytes(), F = fbytes(), ns = nslots;
     hipEvent_t ev;
@@ -530,19 +537,22 @@ template <typename T> struct Engine : EngineBase {
     FWI_HIP(launch_axis_zp<T>(d.nz, tzp, gz, st, axis_args(slot0, na, slot1, 1, 0)));        // Z2
     timer.end(ev, FWI_PASS_Z_PLUS, 3 * ns * S, st);
     ev = timer.begin(st);
-    FWI_HIP(launch_axis_ys<T>(d.ny, ty, gy2, st, axis_args(slot0, na, slot1, 2, 0)));        // Y4
+    FWI_HIP(launch_axis_yv<T>(d.ny, 0, ty, gy, st, axis_args(slot0, na, slot1, 1, 0)));      // Y4: Q, v_y
     timer.end(ev, FWI_PASS_Y_SPLIT, 5 * ns * S, st);
+    ev = timer.begin(st);
+    FWI_HIP(launch_axis_yv<T>(d.ny, 1, ty, gy, st, axis_args(slot0, na, slot1, 1, 0)));      // Y4: R, v_z
+    timer.end(ev, FWI_PASS_Y_SPLIT, 4 * ns * S, st);
     XArgs<T> xa;
     xa.slots = slot_table; xa.slot0 = slot0; xa.na = na; xa.slot1 = slot1;
     xa.d = d; xa.tb = tb; xa.dt_rho = (T)(p.dt / p.rho0);
     const int lpb = x_lines_per_block_vel<T>(d.M);
     ev = timer.begin(st);
-    FWI_HIP(launch_x_vel<T>(d.M, dim3((d.nlines + lpb - 1) / lpb, nslots), st, xa));       // X1
-    timer.end(ev, FWI_PASS_X_VEL, ns * (6 * S + 6 * F), st);
+    FWI_HIP(launch_x_vel<T>(d.M, dim3((d.nlines + lpb - 1) / lpb, nslots), st, xa));       // X1 (v_x)
+    timer.end(ev, FWI_PASS_X_VEL, ns * (2 * S + 2 * F), st);
     if (half_only) return FWI_OK;
     ev = timer.begin(st);
-    FWI_HIP(launch_axis_y<T>(d.ny, false, ty, gy3, st, axis_args(slot0, na, slot1, 3, 0)));  // Y1
-    timer.end(ev, FWI_PASS_Y_FWD, 6 * ns * S, st);
+    FWI_HIP(launch_axis_y<T>(d.ny, false, ty, gy, st, axis_args(slot0, na, slot1, 1, 0)));   // Y1 (v_x)
+    timer.end(ev, FWI_PASS_Y_FWD, 2 * ns * S, st);
     ev = timer.begin(st);
     FWI_HIP(launch_axis_zm<T>(d.nz, tzm, gz3, st, axis_args(slot0, na, slot1, 3, 0)));       // Z1
     timer.end(ev, FWI_PASS_Z_MINUS, 6 * ns * S, st);
@@ -592,7 +602,9 @@ template <typename T> struct Engine : EngineBase {
     char* b = (char*)mem_slots.p + (size_t)s0 * lay.slot_bytes;
     return fill<T>((T*)b, (long long)(n * lay.slot_bytes / sizeof(T)), (T)0, st);
   }
-  int zero_velocity(int s, hipStream_t st) { return fill<T>(slots_host[s].v[0], 3 * d.nfield, (T)0, st); }
+  // the velocity block of a slot: v_x, V_y, V_z (contiguous)
+  long long vel_reals() const { return (long long)(lay.vel_bytes / sizeof(T)); }
+  int zero_velocity(int s, hipStream_t st) { return fill<T>(slots_host[s].v[0], vel_reals(), (T)0, st); }
 
   int check_c(int B, const T* c, hipStream_t st) {
     FWI_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
@@ -705,7 +717,7 @@ template <typename T> struct Engine : EngineBase {
       if ((rc = step_spectral(tr0, B, tr0, B, st, true))) return rc;
       for (int b = 0; b < B; ++b) {
         hipLaunchKernelGGL((k_scale<T>), dim3(4096), dim3(256), 0, st, slots_host[tr0 + b].v[0],
-                           (long long)3 * d.nfield, (T)-1);
+                           vel_reals(), (T)-1);
         FWI_HIP(hipGetLastError());
       }
       a.tr_state_mode = 2;

@@ -51,7 +51,7 @@ namespace fwi {
 #define FWI_AXIS_MAX_NT 512
 #endif
 #ifndef FWI_XVEL_LDS_BUDGET
-#define FWI_XVEL_LDS_BUDGET 5120
+#define FWI_XVEL_LDS_BUDGET 15360
 #endif
 #ifndef FWI_XDEN_LDS_BUDGET
 #define FWI_XDEN_LDS_BUDGET 3072
@@ -121,6 +121,7 @@ template <typename T> struct AxisArgs {
   Tables<T> tb;
   T scale;     // 1 / (nx ny nz)
   T kap_a;     // (c_ref dt / 2)^2
+  T vcoef;     // nx dt / rho0: velocity update of the x-spectrum states
 };
 
 __device__ __forceinline__ int slot_of(int i, int slot0, int na, int slot1) {
@@ -399,6 +400,118 @@ k_axis_y_split(AxisArgs<T> a) {
   }
 }
 
+// Inverse y pass of the time step, fused with the velocity update of v_y and
+// v_z and with their forward y transforms.  v_y and v_z are kept as x
+// spectra V_a = F_x v_a (unnormalised R2C, rows of px complex): their PML
+// factor Lambda^s_a depends on y (a = y) or on z (a = z) only, i.e. it is a
+// constant along every x-line, so v_a <- L_a (L_a v_a - dt/rho0 d+_a p)
+// (Alg. 1 momentum step) commutes with F_x and is applied here, where
+// F_x d+_a p is at hand; the velocity x pass then handles v_x only.  Per slot
+// (grid.y = slots), one launch per part:
+//   part 0: Q (field 0) -> F_y^-1 Q to field 0 (d+_x p, finished by X1);
+//           G = F_y^-1 (i k_y e^{+i k_y dy/2} Q) = F_x(d+_y p) / nx;
+//           V_y <- L_y (L_y V_y - nx dt/rho0 G);  F_y V_y -> field 1
+//   part 1: R (field 2): G = F_y^-1 R = F_x(d+_z p) / nx;
+//           V_z <- L_z (L_z V_z - nx dt/rho0 G);  F_y V_z -> field 2
+// The two parts are separate kernels so that each gets its own register
+// allocation.  L == ny.
+template <typename T, int L, int TW, int NT>
+__device__ __forceinline__ void y_vel_update(cplx<T>* buf, const cplx<T>* twl, const cplx<T>* vs,
+                                             const T* lam_row, T lam_all, T vcoef, cplx<T>* gv, cplx<T>* gout,
+                                             size_t px, int ncol) {
+  using C = cplx<T>;
+  constexpr int E = L * TW;
+  constexpr int EPT = (E + NT - 1) / NT;
+  lds_fft<T, L, TW, TW, NT, true>(buf, twl);
+  // each thread updates the elements it loaded (same element map as the tile load)
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = (int)threadIdx.x + i * NT;
+    if (E % NT == 0 || e < E) {
+      const T lam = lam_row ? lam_row[e / TW] : lam_all;
+      const C g = buf[e];
+      const C vn = cmake<C>(lam * (lam * vs[i].x - vcoef * g.x), lam * (lam * vs[i].y - vcoef * g.y));
+      buf[e] = vn;
+      if (e % TW < ncol) gst(gv + (size_t)(e / TW) * px + e % TW, vn);
+    }
+  }
+  __syncthreads();
+  lds_fft<T, L, TW, TW, NT, false>(buf, twl);
+  tile_store<T, L, TW, NT>(buf, gout, px, ncol);
+}
+
+template <typename T, int L, int TB, int PART>
+__global__ void __launch_bounds__(axis_nt(L, tile_tw<T, TB>()))
+k_axis_y_vel(AxisArgs<T> a) {
+  using C = cplx<T>;
+  constexpr int TW = tile_tw<T, TB>();
+  constexpr int NT = axis_nt(L, TW);
+  constexpr int E = L * TW;
+  constexpr int EPT = (E + NT - 1) / NT;
+  constexpr int TPT = TwRegs<L, NT>::N_PER;
+  __shared__ C buf[L * TW];
+  __shared__ C twl[L];
+  __shared__ C sfl[L];   // part 0: i k_y e^{+i k_y dy/2}
+  __shared__ T lml[L];   // part 0: Lambda^s_y
+  const int ntx = (a.d.px + TW - 1) / TW;   // tiles per spectrum row
+  const int tile = blockIdx.x % ntx;
+  const int z = blockIdx.x / ntx;
+  const Slot<T>& sl = a.slots[slot_of(blockIdx.y, a.slot0, a.na, a.slot1)];
+  const size_t px = a.d.px;
+  const size_t off = (size_t)z * L * px + (size_t)tile * TW;
+  const int ncol = min(TW, (int)px - tile * TW);
+  if constexpr (PART == 0) {
+    C* const gq = sl.spec[0] + off;
+    C q[EPT];
+    {
+      C tt[TPT], ts[TPT];
+      T tl[TPT];
+      tile_prefetch<T, L, TW, NT>(q, gq, px, ncol);
+      tw_prefetch<T, L, NT>(tt, a.tb.tw_y);
+      tw_prefetch<T, L, NT>(ts, a.tb.sfac_p[1]);
+#pragma unroll
+      for (int i = 0; i < TPT; ++i) tl[i] = gld(a.tb.pml_s[1] + min((int)threadIdx.x + i * NT, L - 1));
+      tile_commit<T, L, TW, NT>(buf, q);
+      tw_commit<T, L, NT>(twl, tt);
+      tw_commit<T, L, NT>(sfl, ts);
+#pragma unroll
+      for (int i = 0; i < TPT; ++i) {
+        const int e = (int)threadIdx.x + i * NT;
+        if (L % NT == 0 || e < L) lml[e] = tl[i];
+      }
+    }
+    __syncthreads();
+    lds_fft<T, L, TW, TW, NT, true>(buf, twl);
+    tile_store<T, L, TW, NT>(buf, gq, px, ncol);     // F_y^-1 Q
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = (int)threadIdx.x + i * NT;
+      if (E % NT == 0 || e < E) buf[e] = cmul(sfl[e / TW], q[i]);
+    }
+    C vs[EPT];
+    C* const gv = reinterpret_cast<C*>(sl.v[1]) + off;
+    tile_prefetch<T, L, TW, NT>(vs, gv, px, ncol);     // in flight during the next transform
+    __syncthreads();
+    y_vel_update<T, L, TW, NT>(buf, twl, vs, lml, (T)1, a.vcoef, gv, sl.spec[1] + off, px, ncol);
+  } else {
+    C* const gr = sl.spec[2] + off;
+    C* const gv = reinterpret_cast<C*>(sl.v[2]) + off;
+    C vs[EPT];
+    {
+      C tmp[EPT], tt[TPT];
+      tile_prefetch<T, L, TW, NT>(tmp, gr, px, ncol);
+      tile_prefetch<T, L, TW, NT>(vs, gv, px, ncol);
+      tw_prefetch<T, L, NT>(tt, a.tb.tw_y);
+      tile_commit<T, L, TW, NT>(buf, tmp);
+      tw_commit<T, L, NT>(twl, tt);
+    }
+    const T lz = gld(a.tb.pml_s[2] + z);
+    __syncthreads();
+    y_vel_update<T, L, TW, NT>(buf, twl, vs, nullptr, lz, a.vcoef, gv, gr, px, ncol);
+  }
+}
+
 // ----------------------------------------------------------------------------
 // x passes: LPB consecutive x-lines per workgroup, real <-> half spectrum
 // ----------------------------------------------------------------------------
@@ -597,13 +710,15 @@ template <typename T> struct XArgs {
   T dt_rho;   // dt / rho0
 };
 
-// X1: d+_a p (C2R of the three Z2/Y4 spectra), velocity update
-// v_a <- L^s_a (L^s_a v_a - dt/rho0 d+_a p) (Alg. 1 momentum step), R2C of v_a.
+// X1: d+_x p (C2R of field 0 after the shift factor i k_x e^{+i k_x dx/2}),
+// v_x <- L^s_x (L^s_x v_x - dt/rho0 d+_x p) with L^s_x varying along x (Alg. 1
+// momentum step), R2C of v_x into field 0.  (v_y and v_z are advanced by the
+// inverse y pass, k_axis_y_vel.)
 template <typename T, int M>
 __global__ void __launch_bounds__(X_NT) __attribute__((amdgpu_waves_per_eu(4))) k_x_velocity(XArgs<T> a) {
   using C = cplx<T>;
   constexpr int LPB = x_lpb_vel<T>(M);
-  constexpr int NC = 3 * LPB;
+  constexpr int NC = LPB;
   constexpr int TWP = NC;
   __shared__ C buf[(M + 1) * TWP];
   __shared__ C twl[XTw<M>::N];
@@ -613,30 +728,22 @@ __global__ void __launch_bounds__(X_NT) __attribute__((amdgpu_waves_per_eu(4))) 
   const size_t px = a.d.px;
   const int nx = a.d.nx;
   // velocities and PML factors are prefetched: in flight during the C2R
-  // transforms.  Items of a thread share n when one row of lanes spans a line.
   using Ly = Lanes<LPB, M>;
-  C vv[Ly::NI][3];
+  C vv[Ly::NI];
   C l0f[Ly::NI];          // (Lambda^s_x at x = 2n, 2n + 1)
-  T l1f[Ly::NI], l2f[Ly::NI];
   lanes2d_all<LPB, M>([&](int i, int l, int n, bool) {
-    const int line = l0 + min(l, nl - 1);
-    const size_t lo = (size_t)line * nx;
-#pragma unroll
-    for (int f = 0; f < 3; ++f) vv[i][f] = gld(reinterpret_cast<const C*>(sl.v[f] + lo) + n);
+    const size_t lo = (size_t)(l0 + min(l, nl - 1)) * nx;
+    vv[i] = gld(reinterpret_cast<const C*>(sl.v[0] + lo) + n);
     l0f[i] = gld(reinterpret_cast<const C*>(a.tb.pml_s[0]) + n);
-    l1f[i] = gld(a.tb.pml_s[1] + line % a.d.ny);
-    l2f[i] = gld(a.tb.pml_s[2] + line / a.d.ny);
   });
   {
-    // field 0 holds F_y^-1 Q (Z2): its x shift factor i k_x e^{+i k_x dx/2}
-    // is applied here, in the x wave-number domain
-    C pre[SpecRegs<T, M, LPB, 3>::N], tt[XTw<M>::PER], sx[Lanes<LPB, M + 1>::NI];
-    x_prefetch_spectra<T, M, LPB, 3>(pre, sl.spec, l0, nl, px);
+    C pre[SpecRegs<T, M, LPB, 1>::N], tt[XTw<M>::PER], sx[Lanes<LPB, M + 1>::NI];
+    x_prefetch_spectra<T, M, LPB, 1>(pre, sl.spec, l0, nl, px);
     x_tw_prefetch<T, M>(tt, a.tb);
     lanes2d_all<LPB, M + 1>([&](int i, int, int k, bool) { sx[i] = gld(a.tb.sfac_p[0] + k); });
 #pragma unroll
     for (int i = 0; i < Lanes<LPB, M + 1>::NI; ++i) pre[i] = cmul(sx[i], pre[i]);
-    x_commit_spectra<T, M, LPB, TWP, 3>(buf, pre, 0);
+    x_commit_spectra<T, M, LPB, TWP, 1>(buf, pre, 0);
     x_tw_commit<T, M>(twl, tt);
   }
   __syncthreads();
@@ -645,22 +752,17 @@ __global__ void __launch_bounds__(X_NT) __attribute__((amdgpu_waves_per_eu(4))) 
   lds_fft<T, M, NC, TWP, X_NT, true>(buf, twl);
   lanes2d<LPB, M>([&](int i, int l, int n) {
     if (l >= nl) return;
-    const int line = l0 + l;
-#pragma unroll
-    for (int f = 0; f < 3; ++f) {
-      const C dp = buf[n * TWP + f * LPB + l];
-      const T lx = f == 0 ? l0f[i].x : (f == 1 ? l1f[i] : l2f[i]);
-      const T ly = f == 0 ? l0f[i].y : (f == 1 ? l1f[i] : l2f[i]);
-      const C vn = cmake<C>(lx * (lx * vv[i][f].x - a.dt_rho * dp.x), ly * (ly * vv[i][f].y - a.dt_rho * dp.y));
-      gst(reinterpret_cast<C*>(sl.v[f] + (size_t)line * nx) + n, vn);
-      buf[n * TWP + f * LPB + l] = vn;
-    }
+    const C dp = buf[n * TWP + l];
+    const T lx = l0f[i].x, ly = l0f[i].y;
+    const C vn = cmake<C>(lx * (lx * vv[i].x - a.dt_rho * dp.x), ly * (ly * vv[i].y - a.dt_rho * dp.y));
+    gst(reinterpret_cast<C*>(sl.v[0] + (size_t)(l0 + l) * nx) + n, vn);
+    buf[n * TWP + l] = vn;
   });
   __syncthreads();
   lds_fft<T, M, NC, TWP, X_NT, false>(buf, twl);
   r2c_post<T, M, TWP, NC>(buf, twl + M);
   __syncthreads();
-  x_store_spectra<T, M, LPB, TWP, 3>(buf, sl.spec, 0, l0, nl, px);
+  x_store_spectra<T, M, LPB, TWP, 1>(buf, sl.spec, 0, l0, nl, px);
 }
 
 enum XMode { XM_FWD = 0, XM_PAIR = 1, XM_TRONLY = 2, XM_ADJONLY = 3 };
