@@ -51,7 +51,7 @@ namespace fwi {
 #define FWI_AXIS_MAX_NT 512
 #endif
 #ifndef FWI_XVEL_LDS_BUDGET
-#define FWI_XVEL_LDS_BUDGET 15360
+#define FWI_XVEL_LDS_BUDGET 5120
 #endif
 #ifndef FWI_XDEN_LDS_BUDGET
 #define FWI_XDEN_LDS_BUDGET 3072
