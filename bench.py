@@ -35,7 +35,8 @@ KERNEL_SYMBOLS = {
     "x_vel": "k_x_velocity<float, {m}>",
     "x_den_fwd": "k_x_density<float, {m}, 0>",
     "x_den_pair": "k_x_density<float, {m}, 1>",
-    "y_split": "k_axis_y_vel<float, {ny}, {ty}>",
+    "y_vel_q": "k_axis_y_vel<float, {ny}, {ty}, 0>",
+    "y_vel_r": "k_axis_y_vel<float, {ny}, {ty}, 1>",
 }
 
 

@@ -190,8 +190,9 @@ enum {
   FWI_PASS_X_VEL = 4,    /* C2R, v_x update, R2C                              */
   FWI_PASS_X_DEN_FWD = 5,  /* C2R, density/EOS/sources/sensors/tape, R2C       */
   FWI_PASS_X_DEN_PAIR = 6, /* adjoint + TR density passes with gradient        */
-  FWI_PASS_Y_SPLIT = 7,  /* inverse y-FFT after Z2 with the v_y, v_z update    */
-  FWI_PASS_COUNT = 8
+  FWI_PASS_Y_VEL_Q = 7,  /* inverse y-FFT of Q (Z2) with the v_y update        */
+  FWI_PASS_Y_VEL_R = 8,  /* inverse y-FFT of R (Z2) with the v_z update        */
+  FWI_PASS_COUNT = 9
 };
 
 /* Sampled timing of the pass launches, for roofline measurement: when

@@ -538,10 +538,10 @@ template <typename T> struct Engine : EngineBase {
     timer.end(ev, FWI_PASS_Z_PLUS, 3 * ns * S, st);
     ev = timer.begin(st);
     FWI_HIP(launch_axis_yv<T>(d.ny, 0, ty, gy, st, axis_args(slot0, na, slot1, 1, 0)));      // Y4: Q, v_y
-    timer.end(ev, FWI_PASS_Y_SPLIT, 5 * ns * S, st);
+    timer.end(ev, FWI_PASS_Y_VEL_Q, 5 * ns * S, st);
     ev = timer.begin(st);
     FWI_HIP(launch_axis_yv<T>(d.ny, 1, ty, gy, st, axis_args(slot0, na, slot1, 1, 0)));      // Y4: R, v_z
-    timer.end(ev, FWI_PASS_Y_SPLIT, 4 * ns * S, st);
+    timer.end(ev, FWI_PASS_Y_VEL_R, 4 * ns * S, st);
     XArgs<T> xa;
     xa.slots = slot_table; xa.slot0 = slot0; xa.na = na; xa.slot1 = slot1;
     xa.d = d; xa.tb = tb; xa.dt_rho = (T)(p.dt / p.rho0);

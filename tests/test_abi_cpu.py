@@ -93,8 +93,8 @@ def test_set_tuning_rejects_null_handle_and_bad_values():
 
 def test_autotune_choice_and_cache(tmp_path):
     from paper_2102_00755_amd import autotune
-    per = {64: {"y_fwd": 1.0, "y_inv": 1.0, "y_split": 1.0, "z_minus": 2.0, "z_plus": 1.0},
-           128: {"y_fwd": 0.9, "y_inv": 0.9, "y_split": 1.0, "z_minus": 2.5, "z_plus": 0.5}}
+    per = {64: {"y_fwd": 1.0, "y_inv": 1.0, "y_vel_q": 1.0, "z_minus": 2.0, "z_plus": 1.0},
+           128: {"y_fwd": 0.9, "y_inv": 0.9, "y_vel_q": 1.0, "z_minus": 2.5, "z_plus": 0.5}}
     assert autotune.choose(per) == {"y_tile_bytes": 128, "zm_tile_bytes": 64, "zp_tile_bytes": 128}
     path = str(tmp_path / "sub" / "tuning.json")
     assert autotune.load_cache(path) == {}
