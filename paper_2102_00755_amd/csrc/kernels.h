@@ -1,13 +1,17 @@
 // HIP kernels of one k-space time step (App. B) and of the TR gradient
 // (Alg. 1), written for gfx950.
 //
-// One time step of one simulation is eight launches, each one HBM pass:
+// One time step of one simulation is nine launches, each one HBM pass:
 //   Y3  forward y-FFT of p_hat                       (1 field in place)
-//   Z2  forward z-FFT, x kappa * i k_a e^{+i k_a dx/2} for a = x,y,z,
-//       inverse z-FFT                                 (1 field -> 3 fields)
-//   Y4  inverse y-FFT                                 (3 fields in place)
-//   X1  inverse x (C2R) -> d+_a p, velocity update with PML, forward x (R2C)
-//   Y1  forward y-FFT                                 (3 fields)
+//   Z2  forward z-FFT, x kappa (Q) and x kappa i k_z e^{+i k_z dz/2} (R),
+//       inverse z-FFT                                 (1 field -> 2 fields)
+//   Y4q inverse y-FFT of Q; the same after x i k_y e^{+i k_y dy/2}, which
+//       advances the x spectrum of v_y, then its forward y-FFT
+//   Y4r inverse y-FFT of R, which advances the x spectrum of v_z, then its
+//       forward y-FFT
+//   X1  x i k_x e^{+i k_x dx/2}, inverse x (C2R) -> d+_x p, v_x update with
+//       PML, forward x (R2C)
+//   Y1  forward y-FFT of the x spectrum of v_x        (1 field)
 //   Z1  forward z-FFT, x kappa * i k_a e^{-i k_a dx/2}, inverse z-FFT
 //   Y2  inverse y-FFT                                 (3 fields)
 //   X2  inverse x (C2R) -> d-_a v_a, split-density update with PML, source /
