@@ -208,6 +208,55 @@ int fwi_timing_enable(fwi_handle* h, int32_t every);
  * spectra, fields, sound speed, tape, ring and accumulator, counted once). */
 int fwi_timing_read(fwi_handle* h, int32_t pass, int64_t* launches, double* total_ms, double* total_bytes);
 
+/* ---- Outer loop: stochastic L-BFGS (App. D, Algorithm 2) ------------------
+ * Device vector primitives of the SLBFGS iteration over the unknowns on
+ * Gamma; the gradient itself comes from fwi_gradient.  Vectors are device
+ * arrays of n reals in the given precision (4 float, 8 double), owned by the
+ * caller; all calls are asynchronous on the stream. */
+
+/* Number of Gamma voxels (length of a Gamma-compact vector) of the handle. */
+int fwi_gamma_size(const fwi_handle* h, int64_t* n);
+
+/* compact[k] = full[k-th Gamma voxel in [z][y][x] order] (gather), or
+ * full[k-th Gamma voxel] = compact[k] leaving the rest of full unchanged
+ * (scatter).  full is one [nz][ny][nx] grid in the handle's precision. */
+int fwi_gamma_gather(fwi_handle* h, const void* full, void* compact, fwi_stream_t stream);
+int fwi_gamma_scatter(fwi_handle* h, const void* compact, void* full, fwi_stream_t stream);
+
+/* L-BFGS history of at most m pairs (s, y) of length-n vectors (the buffers S
+ * and Y of Algorithm 2), allocated on `device`; *out NULL on failure
+ * (FWI_ERR_OOM).  Not thread-safe; one history per optimisation. */
+typedef struct fwi_lbfgs fwi_lbfgs;
+int fwi_lbfgs_create(int64_t n, int32_t m, int32_t precision, int32_t device, fwi_lbfgs** out);
+void fwi_lbfgs_destroy(fwi_lbfgs* L);
+
+/* Append the pair (s, y) (copied), dropping the oldest pair when m are
+ * stored, and set rho = 1 / y^T s (FP64 reduction in a fixed order: results
+ * are deterministic).  No curvature check: the pair is used as given. */
+int fwi_lbfgs_push(fwi_lbfgs* L, const void* s, const void* y, fwi_stream_t stream);
+
+/* r = H g, H the L-BFGS inverse-Hessian approximation of the stored pairs with
+ * initial matrix h0 I (two-loop recursion: Nocedal & Wright, Numerical
+ * Optimization, Algorithm 7.4).  r may alias g.  Dot products accumulate in
+ * FP64 in a fixed order; their scalars stay in device memory. */
+int fwi_lbfgs_apply(fwi_lbfgs* L, const void* g, void* r, double h0, fwi_stream_t stream);
+
+/* Number of stored pairs (host bookkeeping, no device access). */
+int fwi_lbfgs_count(const fwi_lbfgs* L, int32_t* count);
+
+/* y = a x + b y (x may be NULL: y = b y); with b = 0, y is not read. */
+int fwi_vec_axpby(int64_t n, double a, const void* x, double b, void* y, int32_t precision, fwi_stream_t stream);
+
+/* x = max(min(x, hi), lo): the projection onto bound constraints (Alg. 2). */
+int fwi_vec_clip(int64_t n, void* x, double lo, double hi, int32_t precision, fwi_stream_t stream);
+
+/* Squared-slowness parametrisation u = 1 / c0^2 (Sec. 2.4 preconditioning):
+ * mode 0: out = 1 / in^2 (c0 -> u); mode 1: out = 1 / sqrt(in) (u -> c0);
+ * mode 2: out = -aux^3 in / 2, the gradient with respect to u from the
+ * gradient `in` with respect to c0 at c0 = aux (dc0/du = -c0^3 / 2). */
+int fwi_vec_sqslowness(int64_t n, int32_t mode, const void* in, const void* aux, void* out, int32_t precision,
+                       fwi_stream_t stream);
+
 /* Human-readable text of a status code (static storage). */
 const char* fwi_status_string(int status);
 

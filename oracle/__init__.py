@@ -17,6 +17,9 @@ Every function here is pinned by a ``-m "not gpu"`` test against something
 other than itself (brute-force DFT, the closed-form single-mode evolution,
 the homogeneous Green's function, exact reversibility, linearity,
 finite differences, the dot-product test, published SplitMix64 outputs).
+``oracle.slbfgs`` holds the stochastic L-BFGS of App. D (Algorithm 2), pinned
+by tests/test_oracle_slbfgs.py.
+
 Parity unpinned: the absolute PML profile and the source pulse shape are
 definitions of this build (the paper gives neither); they are checked only
 for their qualitative property (the PML absorbs) and matched oracle <-> GPU.

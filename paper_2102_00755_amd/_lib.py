@@ -35,7 +35,9 @@ SUPPORTED_LENGTHS = (8, 12, 16, 24, 32, 40, 48, 56, 64, 80, 96, 112, 128, 160, 2
 EXPORTED = (
     "fwi_create", "fwi_destroy", "fwi_workspace_bytes", "fwi_rademacher", "fwi_delays", "fwi_forward",
     "fwi_gradient", "fwi_backward", "fwi_derivative", "fwi_get_tuning", "fwi_set_tuning",
-    "fwi_timing_enable", "fwi_timing_read",
+    "fwi_timing_enable", "fwi_timing_read", "fwi_gamma_size", "fwi_gamma_gather", "fwi_gamma_scatter",
+    "fwi_lbfgs_create", "fwi_lbfgs_destroy", "fwi_lbfgs_push", "fwi_lbfgs_apply", "fwi_lbfgs_count",
+    "fwi_vec_axpby", "fwi_vec_clip", "fwi_vec_sqslowness",
     "fwi_status_string", "fwi_last_error",
 )
 
@@ -108,6 +110,28 @@ def load(path: str = LIB_PATH):
     lib.fwi_get_tuning.restype = c_int
     lib.fwi_set_tuning.argtypes = [h, POINTER(FwiTuning)]
     lib.fwi_set_tuning.restype = c_int
+    lib.fwi_gamma_size.argtypes = [h, POINTER(c_int64)]
+    lib.fwi_gamma_size.restype = c_int
+    lib.fwi_gamma_gather.argtypes = [h, c_void_p, c_void_p, c_void_p]
+    lib.fwi_gamma_gather.restype = c_int
+    lib.fwi_gamma_scatter.argtypes = [h, c_void_p, c_void_p, c_void_p]
+    lib.fwi_gamma_scatter.restype = c_int
+    lib.fwi_lbfgs_create.argtypes = [c_int64, c_int32, c_int32, c_int32, POINTER(c_void_p)]
+    lib.fwi_lbfgs_create.restype = c_int
+    lib.fwi_lbfgs_destroy.argtypes = [c_void_p]
+    lib.fwi_lbfgs_destroy.restype = None
+    lib.fwi_lbfgs_push.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.fwi_lbfgs_push.restype = c_int
+    lib.fwi_lbfgs_apply.argtypes = [c_void_p, c_void_p, c_void_p, c_double, c_void_p]
+    lib.fwi_lbfgs_apply.restype = c_int
+    lib.fwi_lbfgs_count.argtypes = [c_void_p, POINTER(c_int32)]
+    lib.fwi_lbfgs_count.restype = c_int
+    lib.fwi_vec_axpby.argtypes = [c_int64, c_double, c_void_p, c_double, c_void_p, c_int32, c_void_p]
+    lib.fwi_vec_axpby.restype = c_int
+    lib.fwi_vec_clip.argtypes = [c_int64, c_void_p, c_double, c_double, c_int32, c_void_p]
+    lib.fwi_vec_clip.restype = c_int
+    lib.fwi_vec_sqslowness.argtypes = [c_int64, c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]
+    lib.fwi_vec_sqslowness.restype = c_int
     lib.fwi_timing_enable.argtypes = [h, c_int32]
     lib.fwi_timing_enable.restype = c_int
     lib.fwi_timing_read.argtypes = [h, c_int32, POINTER(c_int64), POINTER(c_double), POINTER(c_double)]

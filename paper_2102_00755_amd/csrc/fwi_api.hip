@@ -12,6 +12,7 @@
 
 #include "../../include/fwi.h"
 #include "dispatch.h"
+#include "optim_kernels.h"
 
 using namespace fwi;
 
@@ -302,6 +303,9 @@ struct EngineBase {
   virtual int backward(int B, const void* c, const void* resid, double* misfit, void* grad, int flags,
                        hipStream_t st) = 0;
   virtual int derivative(const void* in, void* out, int axis, int sign, hipStream_t st) = 0;
+  // Gamma-compact vectors: compact[k] = full[gamma voxel k] (gather) or back
+  virtual int gamma_copy(const void* src, void* dst, bool gather, hipStream_t st) = 0;
+  virtual long long gamma_count() const = 0;
   PassTimer timer;
   // axis-pass tile row segments in bytes (run-time tuning, fwi_set_tuning)
   int tile_bytes[3] = {FWI_Y_TILE_BYTES, FWI_ZM_TILE_BYTES, FWI_ZP_TILE_BYTES};
@@ -838,6 +842,19 @@ template <typename T> struct Engine : EngineBase {
     return FWI_OK;
   }
 
+  int gamma_copy(const void* src, void* dst, bool gather, hipStream_t st) override {
+    if (!src || !dst) return fail(FWI_ERR_INVALID_ARG, "NULL vector");
+    FWI_HIP(hipSetDevice(device));
+    const long long n = d.n_gam;
+    if (n == 0) return FWI_OK;
+    const int blocks = (int)std::min<long long>((n + 255) / 256, 8192);
+    if (gather) hipLaunchKernelGGL((k_gather<T>), dim3(blocks), dim3(256), 0, st, (const T*)src, gam_lin, n, (T*)dst);
+    else hipLaunchKernelGGL((k_scatter<T>), dim3(blocks), dim3(256), 0, st, (const T*)src, gam_lin, n, (T*)dst);
+    FWI_HIP(hipGetLastError());
+    return FWI_OK;
+  }
+  long long gamma_count() const override { return d.n_gam; }
+
   int derivative(const void* in, void* out, int axis, int sign, hipStream_t st) override {
     if (!in || !out || axis < 0 || axis > 2 || (sign != 1 && sign != -1))
       return fail(FWI_ERR_INVALID_ARG, "bad derivative arguments");
@@ -871,6 +888,81 @@ struct fwi_handle {
   std::unique_ptr<EngineBase> eng;
   int precision = 4;
 };
+
+// L-BFGS history on the device (Alg. 2 buffers S, Y): a ring of m pairs,
+// rho_j = 1 / y_j^T s_j and the alpha_j of the last two-loop recursion.
+struct fwi_lbfgs {
+  int precision = 4, device = 0, m = 0;
+  long long n = 0;
+  void* S = nullptr;        // [m][n]
+  void* Y = nullptr;        // [m][n]
+  double* sc = nullptr;     // rho[m], alpha[m], coef, part[RED_BLOCKS]
+  int count = 0, head = 0;  // stored pairs; ring slot of the oldest
+  double* rho() const { return sc; }
+  double* alpha() const { return sc + m; }
+  double* coef() const { return sc + 2 * m; }
+  double* part() const { return sc + 2 * m + 1; }
+  char* vec(void* base, int slot) const { return (char*)base + (size_t)slot * n * precision; }
+};
+
+namespace {
+
+int vec_blocks(long long n) { return (int)std::min<long long>((n + 255) / 256, 8192); }
+
+template <typename T>
+int lbfgs_dot(fwi_lbfgs* L, const void* a, const void* b, int mode, const double* rho, const double* alpha,
+              double* out, hipStream_t st) {
+  hipLaunchKernelGGL((k_dot_partial<T>), dim3(RED_BLOCKS), dim3(RED_NT), 0, st, (const T*)a, (const T*)b, L->n,
+                     L->part());
+  FWI_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(RED_NT), 0, st, L->part(), RED_BLOCKS, mode, rho, alpha, out);
+  FWI_HIP(hipGetLastError());
+  return FWI_OK;
+}
+
+template <typename T> int lbfgs_push(fwi_lbfgs* L, const void* s, const void* y, hipStream_t st) {
+  int slot;
+  if (L->count < L->m) {
+    slot = (L->head + L->count) % L->m;
+    L->count++;
+  } else {
+    slot = L->head;
+    L->head = (L->head + 1) % L->m;
+  }
+  const size_t bytes = (size_t)L->n * sizeof(T);
+  FWI_HIP(hipMemcpyAsync(L->vec(L->S, slot), s, bytes, hipMemcpyDeviceToDevice, st));
+  FWI_HIP(hipMemcpyAsync(L->vec(L->Y, slot), y, bytes, hipMemcpyDeviceToDevice, st));
+  return lbfgs_dot<T>(L, L->vec(L->Y, slot), L->vec(L->S, slot), 1, nullptr, nullptr, L->rho() + slot, st);
+}
+
+template <typename T> int lbfgs_apply(fwi_lbfgs* L, const void* g, void* r, double h0, hipStream_t st) {
+  const size_t bytes = (size_t)L->n * sizeof(T);
+  if (g != r) FWI_HIP(hipMemcpyAsync(r, g, bytes, hipMemcpyDeviceToDevice, st));
+  const int nb = vec_blocks(L->n);
+  int rc;
+  for (int j = L->count - 1; j >= 0; --j) {   // newest to oldest: alpha_j = rho_j s_j^T q, q -= alpha_j y_j
+    const int slot = (L->head + j) % L->m;
+    if ((rc = lbfgs_dot<T>(L, L->vec(L->S, slot), r, 2, L->rho() + slot, nullptr, L->alpha() + slot, st))) return rc;
+    hipLaunchKernelGGL((k_axpy_dev<T>), dim3(nb), dim3(256), 0, st, (T*)r, (const T*)L->vec(L->Y, slot),
+                       L->alpha() + slot, -1.0, L->n);
+    FWI_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL((k_axpby<T>), dim3(nb), dim3(256), 0, st, L->n, (T)0, (const T*)nullptr, (T)h0, (T*)r);
+  FWI_HIP(hipGetLastError());
+  for (int j = 0; j < L->count; ++j) {        // oldest to newest: r += (alpha_j - rho_j y_j^T r) s_j
+    const int slot = (L->head + j) % L->m;
+    if ((rc = lbfgs_dot<T>(L, L->vec(L->Y, slot), r, 3, L->rho() + slot, L->alpha() + slot, L->coef(), st)))
+      return rc;
+    hipLaunchKernelGGL((k_axpy_dev<T>), dim3(nb), dim3(256), 0, st, (T*)r, (const T*)L->vec(L->S, slot), L->coef(),
+                       1.0, L->n);
+    FWI_HIP(hipGetLastError());
+  }
+  return FWI_OK;
+}
+
+bool prec_ok(int p) { return p == 4 || p == 8; }
+
+}  // namespace
 
 // ---------------------------------------------------------------------------
 // C-ABI
@@ -997,6 +1089,113 @@ int fwi_timing_read(fwi_handle* h, int32_t pass, int64_t* launches, double* tota
   t.launches[pass] = 0;
   t.ms[pass] = 0;
   t.bytes[pass] = 0;
+  return FWI_OK;
+}
+
+int fwi_gamma_size(const fwi_handle* h, int64_t* n) {
+  if (!h || !n) return fail(FWI_ERR_INVALID_ARG, "bad arguments");
+  *n = h->eng->gamma_count();
+  return FWI_OK;
+}
+
+int fwi_gamma_gather(fwi_handle* h, const void* full, void* compact, fwi_stream_t stream) {
+  if (!h) return fail(FWI_ERR_INVALID_ARG, "handle is NULL");
+  return h->eng->gamma_copy(full, compact, true, (hipStream_t)stream);
+}
+
+int fwi_gamma_scatter(fwi_handle* h, const void* compact, void* full, fwi_stream_t stream) {
+  if (!h) return fail(FWI_ERR_INVALID_ARG, "handle is NULL");
+  return h->eng->gamma_copy(compact, full, false, (hipStream_t)stream);
+}
+
+int fwi_lbfgs_create(int64_t n, int32_t m, int32_t precision, int32_t device, fwi_lbfgs** out) {
+  if (!out) return fail(FWI_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (n <= 0 || m <= 0 || !prec_ok(precision)) return fail(FWI_ERR_INVALID_ARG, "bad L-BFGS sizes");
+  std::unique_ptr<fwi_lbfgs> L(new fwi_lbfgs());
+  L->precision = precision; L->device = device; L->m = m; L->n = n;
+  FWI_HIP(hipSetDevice(device));
+  const size_t vb = (size_t)m * n * precision;
+  if (hipMalloc(&L->S, vb) != hipSuccess || hipMalloc(&L->Y, vb) != hipSuccess ||
+      hipMalloc((void**)&L->sc, (2 * (size_t)m + 1 + RED_BLOCKS) * sizeof(double)) != hipSuccess) {
+    if (L->S) (void)hipFree(L->S);
+    if (L->Y) (void)hipFree(L->Y);
+    if (L->sc) (void)hipFree(L->sc);
+    return fail(FWI_ERR_OOM, "L-BFGS history allocation failed");
+  }
+  *out = L.release();
+  return FWI_OK;
+}
+
+void fwi_lbfgs_destroy(fwi_lbfgs* L) {
+  if (!L) return;
+  (void)hipSetDevice(L->device);
+  (void)hipFree(L->S);
+  (void)hipFree(L->Y);
+  (void)hipFree(L->sc);
+  delete L;
+}
+
+int fwi_lbfgs_push(fwi_lbfgs* L, const void* s, const void* y, fwi_stream_t stream) {
+  if (!L || !s || !y) return fail(FWI_ERR_INVALID_ARG, "bad arguments");
+  FWI_HIP(hipSetDevice(L->device));
+  return L->precision == 4 ? lbfgs_push<float>(L, s, y, (hipStream_t)stream)
+                           : lbfgs_push<double>(L, s, y, (hipStream_t)stream);
+}
+
+int fwi_lbfgs_apply(fwi_lbfgs* L, const void* g, void* r, double h0, fwi_stream_t stream) {
+  if (!L || !g || !r) return fail(FWI_ERR_INVALID_ARG, "bad arguments");
+  FWI_HIP(hipSetDevice(L->device));
+  return L->precision == 4 ? lbfgs_apply<float>(L, g, r, h0, (hipStream_t)stream)
+                           : lbfgs_apply<double>(L, g, r, h0, (hipStream_t)stream);
+}
+
+int fwi_lbfgs_count(const fwi_lbfgs* L, int32_t* count) {
+  if (!L || !count) return fail(FWI_ERR_INVALID_ARG, "bad arguments");
+  *count = L->count;
+  return FWI_OK;
+}
+
+int fwi_vec_axpby(int64_t n, double a, const void* x, double b, void* y, int32_t precision, fwi_stream_t stream) {
+  if (n < 0 || !y || !prec_ok(precision)) return fail(FWI_ERR_INVALID_ARG, "bad arguments");
+  if (n == 0) return FWI_OK;
+  const hipStream_t st = (hipStream_t)stream;
+  if (precision == 4)
+    hipLaunchKernelGGL((k_axpby<float>), dim3(vec_blocks(n)), dim3(256), 0, st, (long long)n, (float)a,
+                       (const float*)x, (float)b, (float*)y);
+  else
+    hipLaunchKernelGGL((k_axpby<double>), dim3(vec_blocks(n)), dim3(256), 0, st, (long long)n, a, (const double*)x, b,
+                       (double*)y);
+  FWI_HIP(hipGetLastError());
+  return FWI_OK;
+}
+
+int fwi_vec_clip(int64_t n, void* x, double lo, double hi, int32_t precision, fwi_stream_t stream) {
+  if (n < 0 || !x || !prec_ok(precision) || !(lo <= hi)) return fail(FWI_ERR_INVALID_ARG, "bad arguments");
+  if (n == 0) return FWI_OK;
+  const hipStream_t st = (hipStream_t)stream;
+  if (precision == 4)
+    hipLaunchKernelGGL((k_clip<float>), dim3(vec_blocks(n)), dim3(256), 0, st, (long long)n, (float*)x, (float)lo,
+                       (float)hi);
+  else
+    hipLaunchKernelGGL((k_clip<double>), dim3(vec_blocks(n)), dim3(256), 0, st, (long long)n, (double*)x, lo, hi);
+  FWI_HIP(hipGetLastError());
+  return FWI_OK;
+}
+
+int fwi_vec_sqslowness(int64_t n, int32_t mode, const void* in, const void* aux, void* out, int32_t precision,
+                       fwi_stream_t stream) {
+  if (n < 0 || !in || !out || mode < 0 || mode > 2 || (mode == 2 && !aux) || !prec_ok(precision))
+    return fail(FWI_ERR_INVALID_ARG, "bad arguments");
+  if (n == 0) return FWI_OK;
+  const hipStream_t st = (hipStream_t)stream;
+  if (precision == 4)
+    hipLaunchKernelGGL((k_sqslowness<float>), dim3(vec_blocks(n)), dim3(256), 0, st, (long long)n, mode,
+                       (const float*)in, (const float*)aux, (float*)out);
+  else
+    hipLaunchKernelGGL((k_sqslowness<double>), dim3(vec_blocks(n)), dim3(256), 0, st, (long long)n, mode,
+                       (const double*)in, (const double*)aux, (double*)out);
+  FWI_HIP(hipGetLastError());
   return FWI_OK;
 }
 
