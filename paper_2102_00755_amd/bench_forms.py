@@ -2,6 +2,7 @@
 
     python -m paper_2102_00755_amd.bench_forms batched [--batch 16] [--nt 600]
     python -m paper_2102_00755_amd.bench_forms serve [--requests 60] [--seconds-scale 1]
+    python -m paper_2102_00755_amd.bench_forms lbfgs [--n 4954176] [--m 64]
 
 batched : 16 independent Rademacher-encoded TR gradients on 128^3 (phantom
           seeds 300..315, encoding seeds 1300..1315), run (a) one after
@@ -14,6 +15,8 @@ serve   : Poisson-arriving forward / gradient requests (50/50) over the grid
           rate is set to ~80 % of the measured single-stream capacity;
           reports p50/p99 latency and Mcell-steps/s against the same requests
           solved one at a time.
+lbfgs   : the SLBFGS two-loop recursion (64 pairs) and pair push at |Gamma| of
+          the full workload, with their algorithmic bandwidth.
 Prints one JSON line per run.  Inputs are synthetic (synth/).
 """
 
@@ -163,16 +166,54 @@ def serve(args) -> dict:
     }
 
 
+def lbfgs(args) -> dict:
+    """Two-loop recursion and pair push of the SLBFGS outer loop at the full
+    workload's unknown count (|Gamma| = 4 954 176 voxels, FP32, m = 64 pairs)."""
+    from .slbfgs import LbfgsHistory, VecOps
+    dev = torch.device("cuda", 0)
+    n, m = args.n, args.m
+    ops = VecOps(dev, torch.float32)
+    hist = LbfgsHistory(n, m, ops)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(5)
+    s = torch.randn(n, device=dev, generator=gen)
+    y = s + 0.1 * torch.randn(n, device=dev, generator=gen)
+    g = torch.randn(n, device=dev, generator=gen)
+    r = torch.empty_like(g)
+    for _ in range(m):
+        hist.push(s, y)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        hist.apply(g, r, 1.0)
+    torch.cuda.synchronize()
+    t_apply = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        hist.push(s, y)
+    torch.cuda.synchronize()
+    t_push = (time.perf_counter() - t0) / reps
+    hist.close()
+    # per pair and loop: a dot (2 vectors read) and an axpy (2 read, 1 written)
+    bytes_apply = 2.0 * m * 5 * n * 4 + 2 * n * 4
+    return {"form": "lbfgs", "n": n, "m": m, "dtype": "f32", "apply_ms": t_apply * 1e3,
+            "apply_GBps_algorithmic": bytes_apply / t_apply / 1e9, "push_ms": t_push * 1e3,
+            "note": "two applies and one push per SLBFGS iteration, against two TR gradients"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("form", choices=["batched", "serve"])
+    ap.add_argument("form", choices=["batched", "serve", "lbfgs"])
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--nt", type=int, default=None)
     ap.add_argument("--requests", type=int, default=60)
     ap.add_argument("--inflight", type=int, default=4)
     ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--n", type=int, default=4954176)
+    ap.add_argument("--m", type=int, default=64)
     args = ap.parse_args()
-    res = batched(args) if args.form == "batched" else serve(args)
+    res = {"batched": batched, "serve": serve, "lbfgs": lbfgs}[args.form](args)
     print(json.dumps(res), flush=True)
 
 
