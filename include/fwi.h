@@ -257,6 +257,32 @@ int fwi_vec_clip(int64_t n, void* x, double lo, double hi, int32_t precision, fw
 int fwi_vec_sqslowness(int64_t n, int32_t mode, const void* in, const void* aux, void* out, int32_t precision,
                        fwi_stream_t stream);
 
+/* ---- Grid transfers of the coarse-to-fine scheme (Sec. 2.4, App. C) -------- */
+
+/* Fourier interpolation of the real field `in` on the coarse handle's grid to
+ * `out` on the fine handle's grid (both [nz][ny][nx] device arrays of the
+ * handles' common precision; the grids must cover the same box: n_a dx equal
+ * per axis, each fine size >= the coarse one).  The coarse DFT is embedded in
+ * the fine frequency grid (zeros elsewhere; the Nyquist bin of an even coarse
+ * axis split in halves over +-N/2) and transformed back; window = 1 multiplies
+ * by the separable Blackman window of the coarse band, 0.42 + 0.5 cos(pi k/K)
+ * + 0.08 cos(2 pi k/K), K = N_coarse/2 per axis (App. C smoothing), window = 0
+ * by nothing.  Uses the handles' scratch spectra (a later fwi_backward needs a
+ * new FWI_SAVE_TAPE forward).  Same device for both handles. */
+int fwi_interp_fourier(fwi_handle* coarse, fwi_handle* fine, const void* in, void* out, int32_t window,
+                       fwi_stream_t stream);
+
+/* Band-limited resampling of time series in [nt_in][n_ch] (step dt_in) to
+ * out [nt_out][n_ch] (step dt_out), with a low-pass cut-off f_cut [Hz]: the
+ * Kaiser-windowed sinc
+ *   out[m] = scale sum_n in[n] 2 f_cut dt_in sinc(2 f_cut tau) I0(beta sqrt(1 - (tau/t_window)^2)) / I0(beta),
+ *   tau = m dt_out - n dt_in, terms with |tau| > t_window omitted
+ * (App. C: sources and data to the coarse time step; data with
+ * scale = eta^(d-1)).  Device arrays; FP64 accumulation. */
+int fwi_resample_time(int32_t nt_in, int32_t n_ch, const void* in, double dt_in, int32_t nt_out, double dt_out,
+                      double f_cut, double beta, double t_window, double scale, void* out, int32_t precision,
+                      fwi_stream_t stream);
+
 /* Human-readable text of a status code (static storage). */
 const char* fwi_status_string(int status);
 

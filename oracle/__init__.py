@@ -18,7 +18,8 @@ other than itself (brute-force DFT, the closed-form single-mode evolution,
 the homogeneous Green's function, exact reversibility, linearity,
 finite differences, the dot-product test, published SplitMix64 outputs).
 ``oracle.slbfgs`` holds the stochastic L-BFGS of App. D (Algorithm 2), pinned
-by tests/test_oracle_slbfgs.py.
+by tests/test_oracle_slbfgs.py; ``oracle.multigrid`` the grid transfers of
+App. C, pinned by tests/test_oracle_multigrid.py.
 
 Parity unpinned: the absolute PML profile and the source pulse shape are
 definitions of this build (the paper gives neither); they are checked only

@@ -37,7 +37,7 @@ EXPORTED = (
     "fwi_gradient", "fwi_backward", "fwi_derivative", "fwi_get_tuning", "fwi_set_tuning",
     "fwi_timing_enable", "fwi_timing_read", "fwi_gamma_size", "fwi_gamma_gather", "fwi_gamma_scatter",
     "fwi_lbfgs_create", "fwi_lbfgs_destroy", "fwi_lbfgs_push", "fwi_lbfgs_apply", "fwi_lbfgs_count",
-    "fwi_vec_axpby", "fwi_vec_clip", "fwi_vec_sqslowness",
+    "fwi_vec_axpby", "fwi_vec_clip", "fwi_vec_sqslowness", "fwi_interp_fourier", "fwi_resample_time",
     "fwi_status_string", "fwi_last_error",
 )
 
@@ -132,6 +132,11 @@ def load(path: str = LIB_PATH):
     lib.fwi_vec_clip.restype = c_int
     lib.fwi_vec_sqslowness.argtypes = [c_int64, c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]
     lib.fwi_vec_sqslowness.restype = c_int
+    lib.fwi_interp_fourier.argtypes = [h, h, c_void_p, c_void_p, c_int32, c_void_p]
+    lib.fwi_interp_fourier.restype = c_int
+    lib.fwi_resample_time.argtypes = [c_int32, c_int32, c_void_p, c_double, c_int32, c_double, c_double, c_double,
+                                      c_double, c_double, c_void_p, c_int32, c_void_p]
+    lib.fwi_resample_time.restype = c_int
     lib.fwi_timing_enable.argtypes = [h, c_int32]
     lib.fwi_timing_enable.restype = c_int
     lib.fwi_timing_read.argtypes = [h, c_int32, POINTER(c_int64), POINTER(c_double), POINTER(c_double)]

@@ -3,6 +3,7 @@
     python -m paper_2102_00755_amd.bench_forms batched [--batch 16] [--nt 600]
     python -m paper_2102_00755_amd.bench_forms serve [--requests 60] [--seconds-scale 1]
     python -m paper_2102_00755_amd.bench_forms lbfgs [--n 4954176] [--m 64]
+    python -m paper_2102_00755_amd.bench_forms multigrid
 
 batched : 16 independent Rademacher-encoded TR gradients on 128^3 (phantom
           seeds 300..315, encoding seeds 1300..1315), run (a) one after
@@ -17,6 +18,7 @@ serve   : Poisson-arriving forward / gradient requests (50/50) over the grid
           solved one at a time.
 lbfgs   : the SLBFGS two-loop recursion (64 pairs) and pair push at |Gamma| of
           the full workload, with their algorithmic bandwidth.
+multigrid: grid transfers between the 1 mm and 0.5 mm levels of the full box.
 Prints one JSON line per run.  Inputs are synthetic (synth/).
 """
 
@@ -202,9 +204,49 @@ def lbfgs(args) -> dict:
             "note": "two applies and one push per SLBFGS iteration, against two TR gradients"}
 
 
+def multigrid(args) -> dict:
+    """Grid transfers between the 224x224x112 (1 mm) and 448x448x224 (0.5 mm)
+    levels: Fourier interpolation with Blackman smoothing of a speed field,
+    and windowed-sinc resampling of 1024-receiver data from 2200 to 1100 steps."""
+    from synth import make_config
+    from .multigrid import coarse_cutoff, coarse_level, data_scale, interp_up, resample_time
+    fine = make_config("full")
+    kw = fwi.problem_kwargs(fine, nt=4)
+    hf = fwi.Handle(**kw)
+    from synth.configs import make_small
+    coarse = make_small(shape=(112, 224, 224), dx=2 * fine.dx, nt=4, pml=10, layer=2, precision=4,
+                        n_src=1, n_rec=2, r_transducer=6.0, r_gamma=4.0)
+    hc = fwi.Handle.from_problem(coarse)
+    dev = hf.device
+    u = torch.full(hc.shape, 1500.0, device=dev)
+    interp_up(hc, hf, u)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = interp_up(hc, hf, u)
+    torch.cuda.synchronize()
+    t_interp = (time.perf_counter() - t0) / reps
+    dt_c, nt_c = coarse_level(fine.dt, fine.nt, 2.0)
+    f = torch.randn((fine.nt, fine.n_rec), device=dev)
+    resample_time(f, fine.dt, dt_c, nt_c, coarse_cutoff(fine.c_min, 2 * fine.dx), scale=data_scale(2.0))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g = resample_time(f, fine.dt, dt_c, nt_c, coarse_cutoff(fine.c_min, 2 * fine.dx), scale=data_scale(2.0))
+    torch.cuda.synchronize()
+    t_res = (time.perf_counter() - t0) / reps
+    ok = bool(torch.isfinite(out).all()) and abs(float(out.mean()) - 1500.0) < 1e-2
+    hc.close()
+    hf.close()
+    return {"form": "multigrid", "interp_ms": t_interp * 1e3, "interp": "224x224x112 -> 448x448x224 FP32",
+            "resample_ms": t_res * 1e3, "resample": f"[{fine.nt}, {fine.n_rec}] -> [{nt_c}, {fine.n_rec}] FP32",
+            "constant_preserved": ok}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("form", choices=["batched", "serve", "lbfgs"])
+    ap.add_argument("form", choices=["batched", "serve", "lbfgs", "multigrid"])
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--nt", type=int, default=None)
     ap.add_argument("--requests", type=int, default=60)
@@ -213,7 +255,7 @@ def main():
     ap.add_argument("--n", type=int, default=4954176)
     ap.add_argument("--m", type=int, default=64)
     args = ap.parse_args()
-    res = {"batched": batched, "serve": serve, "lbfgs": lbfgs}[args.form](args)
+    res = {"batched": batched, "serve": serve, "lbfgs": lbfgs, "multigrid": multigrid}[args.form](args)
     print(json.dumps(res), flush=True)
 
 

@@ -22,6 +22,8 @@ inline bool length_supported(int L) {
 // (tb = row segment of an axis-pass tile in bytes: 64 or 128).
 template <typename T>
 hipError_t launch_axis_y(int L, bool inv, int tb, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
+template <typename T>
+hipError_t launch_axis_z(int L, bool inv, int tb, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
 template <typename T> hipError_t launch_axis_zm(int L, int tb, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
 template <typename T> hipError_t launch_axis_zp(int L, int tb, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
 template <typename T> hipError_t launch_axis_ys(int L, int tb, dim3 grid, hipStream_t st, const AxisArgs<T>& a);

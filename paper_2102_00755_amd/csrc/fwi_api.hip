@@ -306,6 +306,13 @@ struct EngineBase {
   // Gamma-compact vectors: compact[k] = full[gamma voxel k] (gather) or back
   virtual int gamma_copy(const void* src, void* dst, bool gather, hipStream_t st) = 0;
   virtual long long gamma_count() const = 0;
+  // whole-grid 3D transform through the scratch slot's first spectrum:
+  // forward = x R2C, y, z (unnormalised) of a real field; inverse = z, y, x C2R
+  virtual int transform3d(const void* in, void* out, bool forward, hipStream_t st) = 0;
+  virtual void* spectrum() = 0;
+  virtual Dims dims() const = 0;
+  virtual double spacing() const = 0;
+  virtual int dev() const = 0;
   PassTimer timer;
   // axis-pass tile row segments in bytes (run-time tuning, fwi_set_tuning)
   int tile_bytes[3] = {FWI_Y_TILE_BYTES, FWI_ZM_TILE_BYTES, FWI_ZP_TILE_BYTES};
@@ -855,6 +862,34 @@ template <typename T> struct Engine : EngineBase {
   }
   long long gamma_count() const override { return d.n_gam; }
 
+  int transform3d(const void* in, void* out, bool forward, hipStream_t st) override {
+    FWI_HIP(hipSetDevice(device));
+    const int s = p.batch;   // scratch: the first forward slot
+    tape_valid = false;
+    XArgs<T> xa;
+    xa.slots = slot_table; xa.slot0 = s; xa.na = 1; xa.slot1 = s;
+    xa.d = d; xa.tb = tb; xa.dt_rho = (T)0;
+    const int lpb = x_lines_per_block<T>(d.M);
+    const dim3 gx((d.nlines + lpb - 1) / lpb, 1);
+    const int ty = tile_bytes[AK_Y], tz = tile_bytes[AK_ZMINUS];
+    if (forward) {
+      if (!in) return fail(FWI_ERR_INVALID_ARG, "NULL field");
+      FWI_HIP(launch_x_r2c<T>(d.M, gx, st, xa, (const T*)in, 0));
+      FWI_HIP(launch_axis_y<T>(d.ny, false, ty, dim3(ntx(AK_Y) * d.nz, 1), st, axis_args(s, 1, s, 1, 0)));
+      FWI_HIP(launch_axis_z<T>(d.nz, false, tz, dim3(ntx(AK_ZMINUS) * d.ny, 1), st, axis_args(s, 1, s, 1, 0)));
+    } else {
+      if (!out) return fail(FWI_ERR_INVALID_ARG, "NULL field");
+      FWI_HIP(launch_axis_z<T>(d.nz, true, tz, dim3(ntx(AK_ZMINUS) * d.ny, 1), st, axis_args(s, 1, s, 1, 0)));
+      FWI_HIP(launch_axis_y<T>(d.ny, true, ty, dim3(ntx(AK_Y) * d.nz, 1), st, axis_args(s, 1, s, 1, 0)));
+      FWI_HIP(launch_x_c2r<T>(d.M, gx, st, xa, (T*)out, 0, nullptr));
+    }
+    return FWI_OK;
+  }
+  void* spectrum() override { return slots_host[p.batch].spec[0]; }
+  Dims dims() const override { return d; }
+  double spacing() const override { return p.dx; }
+  int dev() const override { return device; }
+
   int derivative(const void* in, void* out, int axis, int sign, hipStream_t st) override {
     if (!in || !out || axis < 0 || axis > 2 || (sign != 1 && sign != -1))
       return fail(FWI_ERR_INVALID_ARG, "bad derivative arguments");
@@ -1106,6 +1141,56 @@ int fwi_gamma_gather(fwi_handle* h, const void* full, void* compact, fwi_stream_
 int fwi_gamma_scatter(fwi_handle* h, const void* compact, void* full, fwi_stream_t stream) {
   if (!h) return fail(FWI_ERR_INVALID_ARG, "handle is NULL");
   return h->eng->gamma_copy(compact, full, false, (hipStream_t)stream);
+}
+
+int fwi_interp_fourier(fwi_handle* coarse, fwi_handle* fine, const void* in, void* out, int32_t window,
+                       fwi_stream_t stream) {
+  if (!coarse || !fine || !in || !out || (window != 0 && window != 1))
+    return fail(FWI_ERR_INVALID_ARG, "bad arguments");
+  if (coarse->precision != fine->precision) return fail(FWI_ERR_INVALID_ARG, "precisions differ");
+  EngineBase& ec = *coarse->eng;
+  EngineBase& ef = *fine->eng;
+  if (ec.dev() != ef.dev()) return fail(FWI_ERR_INVALID_ARG, "handles on different devices");
+  const Dims dc = ec.dims(), df = ef.dims();
+  if (dc.nx > df.nx || dc.ny > df.ny || dc.nz > df.nz) return fail(FWI_ERR_INVALID_ARG, "fine grid smaller");
+  const double lc[3] = {dc.nx * ec.spacing(), dc.ny * ec.spacing(), dc.nz * ec.spacing()};
+  const double lf[3] = {df.nx * ef.spacing(), df.ny * ef.spacing(), df.nz * ef.spacing()};
+  for (int a = 0; a < 3; ++a)
+    if (std::fabs(lc[a] - lf[a]) > 1e-9 * lf[a]) return fail(FWI_ERR_INVALID_ARG, "grids cover different boxes");
+  const hipStream_t st = (hipStream_t)stream;
+  int rc;
+  if ((rc = ec.transform3d(in, nullptr, true, st))) return rc;
+  FWI_HIP(hipSetDevice(ef.dev()));
+  const long long nf = (long long)df.px * df.ny * df.nz;
+  const double scale = 1.0 / ((double)dc.nx * dc.ny * dc.nz);
+  const int blocks = (int)std::min<long long>((nf + 255) / 256, 16384);
+  if (fine->precision == 4)
+    hipLaunchKernelGGL((k_spec_embed<float>), dim3(blocks), dim3(256), 0, st, (const cplx<float>*)ec.spectrum(), dc,
+                       (cplx<float>*)ef.spectrum(), df, window, scale);
+  else
+    hipLaunchKernelGGL((k_spec_embed<double>), dim3(blocks), dim3(256), 0, st, (const cplx<double>*)ec.spectrum(),
+                       dc, (cplx<double>*)ef.spectrum(), df, window, scale);
+  FWI_HIP(hipGetLastError());
+  return ef.transform3d(nullptr, out, false, st);
+}
+
+int fwi_resample_time(int32_t nt_in, int32_t n_ch, const void* in, double dt_in, int32_t nt_out, double dt_out,
+                      double f_cut, double beta, double t_window, double scale, void* out, int32_t precision,
+                      fwi_stream_t stream) {
+  if (nt_in <= 0 || n_ch <= 0 || nt_out <= 0 || !in || !out || !(dt_in > 0) || !(dt_out > 0) || !(f_cut > 0) ||
+      !(beta >= 0) || !(t_window > 0) || !prec_ok(precision))
+    return fail(FWI_ERR_INVALID_ARG, "bad arguments");
+  const hipStream_t st = (hipStream_t)stream;
+  const long long n = (long long)nt_out * n_ch;
+  const int blocks = (int)std::min<long long>((n + 255) / 256, 16384);
+  if (precision == 4)
+    hipLaunchKernelGGL((k_resample_time<float>), dim3(blocks), dim3(256), 0, st, (const float*)in, nt_in, n_ch, dt_in,
+                       (float*)out, nt_out, dt_out, f_cut, beta, t_window, scale);
+  else
+    hipLaunchKernelGGL((k_resample_time<double>), dim3(blocks), dim3(256), 0, st, (const double*)in, nt_in, n_ch,
+                       dt_in, (double*)out, nt_out, dt_out, f_cut, beta, t_window, scale);
+  FWI_HIP(hipGetLastError());
+  return FWI_OK;
 }
 
 int fwi_lbfgs_create(int64_t n, int32_t m, int32_t precision, int32_t device, fwi_lbfgs** out) {

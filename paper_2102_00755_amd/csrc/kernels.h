@@ -224,6 +224,31 @@ k_axis_y(AxisArgs<T> a) {
   tile_store<T, L, TW, NT>(buf, g, px, ncol);
 }
 
+// Plain z pass: in-place FFT along z of nf fields per slot (grid transfers of
+// the coarse-to-fine scheme).  L == nz.
+template <typename T, int L, bool INV, int TB>
+__global__ void __launch_bounds__(axis_nt(L, tile_tw<T, TB>()))
+k_axis_z(AxisArgs<T> a) {
+  using C = cplx<T>;
+  constexpr int TW = tile_tw<T, TB>();
+  constexpr int NT = axis_nt(L, TW);
+  __shared__ C buf[L * TW];
+  __shared__ C twl[L];
+  const int ntx = (a.d.px + TW - 1) / TW;   // tiles per spectrum row
+  const int tile = blockIdx.x % ntx;
+  const int y = blockIdx.x / ntx;
+  const int s = slot_of(blockIdx.y / a.nf, a.slot0, a.na, a.slot1);
+  const int f = a.f0 + blockIdx.y % a.nf;
+  const size_t px = a.d.px;
+  const size_t rstride = (size_t)a.d.ny * px;
+  C* g = a.slots[s].spec[f] + (size_t)y * px + (size_t)tile * TW;
+  const int ncol = min(TW, (int)px - tile * TW);
+  tile_load<T, L, TW, NT>(buf, g, rstride, ncol, twl, a.tb.tw_z);
+  __syncthreads();
+  lds_fft<T, L, TW, TW, NT, INV>(buf, twl);
+  tile_store<T, L, TW, NT>(buf, g, rstride, ncol);
+}
+
 // k-space multipliers of the elements a thread owns in a z tile: thread t
 // owns rows r_i = t / TW + i NT / TW of column c = t % TW (NT is a multiple
 // of TW), so kx is fixed per thread.  The tables are read before the tile's
