@@ -182,7 +182,9 @@ class Handle:
         return tr
 
     def gradient(self, c, src_sig, w, obs, check=False, out=None) -> Tuple[torch.Tensor, torch.Tensor]:
-        """(misfit [B] float64, gradient [B, nz, ny, nx]) of the encoded TR gradient."""
+        """(misfit [B] float64, gradient [B, nz, ny, nx]) of the encoded TR gradient.
+        check=True validates c against [c_min, c_max] and the result for
+        finiteness (both read a device flag back, so the call synchronises)."""
         c = self._t(c, self.shape)
         B = c.shape[0]
         src = self._t(src_sig, (self.nt, self.n_src))
@@ -195,22 +197,24 @@ class Handle:
             grad = out
         else:
             grad = torch.empty((B, *self.shape), device=self.device, dtype=self.dtype)
-        flags = (L.FWI_CHECK_INPUT if check else 0) | (L.FWI_GRAPH if self.use_graph else 0)
+        flags = (L.FWI_CHECK_INPUT | L.FWI_CHECK_FINITE if check else 0) | (L.FWI_GRAPH if self.use_graph else 0)
         flags |= L.FWI_TR_FINAL_STATE if self.tr_final_state else 0
         self.tape_token += 1
         _check(self._lib.fwi_gradient(self._h, B, c.data_ptr(), src.data_ptr(), w.data_ptr(), obs.data_ptr(),
                                       mis.data_ptr(), grad.data_ptr(), flags, self._stream()), "fwi_gradient")
         return mis, grad
 
-    def backward(self, c, residual) -> Tuple[torch.Tensor, torch.Tensor]:
+    def backward(self, c, residual, check=False) -> Tuple[torch.Tensor, torch.Tensor]:
         """(1/2 ||r||^2 [B], (df/dc)^T r on Gamma) using the tape of the last
-        forward(save_tape=True) call with the same batch."""
+        forward(save_tape=True) call with the same batch (FwiError with
+        FWI_ERR_NO_TAPE otherwise); check as in gradient()."""
         c = self._t(c, self.shape)
         B = c.shape[0]
         r = self._t(residual, (self.nt, self.n_rec))
         mis = torch.empty((B,), device=self.device, dtype=torch.float64)
         grad = torch.empty((B, *self.shape), device=self.device, dtype=self.dtype)
         flags = (L.FWI_GRAPH if self.use_graph else 0) | (L.FWI_TR_FINAL_STATE if self.tr_final_state else 0)
+        flags |= (L.FWI_CHECK_INPUT | L.FWI_CHECK_FINITE) if check else 0
         _check(self._lib.fwi_backward(self._h, B, c.data_ptr(), r.data_ptr(), mis.data_ptr(), grad.data_ptr(),
                                       flags, self._stream()), "fwi_backward")
         return mis, grad

@@ -105,3 +105,56 @@ def test_autotune_choice_and_cache(tmp_path):
     with open(path, "w") as f:
         f.write("not json")
     assert autotune.load_cache(path) == {}
+
+
+def _create_status(mutate_params=None, mutate_geo=None):
+    """fwi_create status for a valid small problem with one change; the
+    argument checks run before any device call, so this needs no GPU."""
+    from paper_2102_00755_amd import fwi
+    L, lib = _lib()
+    prob = make_small(shape=(16, 24, 32), nt=10, precision=4)
+    kw = fwi.problem_kwargs(prob)
+    geo_kw = dict(src=np.array(kw["src_ijk"]), rec=np.array(kw["rec_ijk"]), gamma=kw["gamma"].copy(),
+                  boundary=kw["boundary"].copy())
+    if mutate_geo:
+        mutate_geo(geo_kw, prob)
+    p = fwi._params(kw["shape"], kw["dx"], kw["dt"], kw["nt"], kw["c_ref"], kw["c_min"], kw["c_max"], kw["rho0"],
+                    kw["pml"], kw["pml_alpha"], kw["precision"], 1)
+    if mutate_params:
+        mutate_params(p)
+    geo = fwi._Geometry(geo_kw["src"], geo_kw["rec"], geo_kw["gamma"], geo_kw["boundary"])
+    h = ctypes.c_void_p(None)
+    rc = lib.fwi_create(ctypes.byref(p), ctypes.byref(geo.c), 0, ctypes.byref(h))
+    assert not h.value or rc == L.FWI_OK
+    return rc, L
+
+
+def test_create_rejects_invalid_arguments_before_any_device_call():
+    rc, L = _create_status(lambda p: setattr(p, "nx", 30))
+    assert rc == L.FWI_ERR_UNSUPPORTED                       # nx/2 = 15 not a supported length
+    assert _create_status(lambda p: setattr(p, "precision", 5))[0] == L.FWI_ERR_INVALID_ARG
+    assert _create_status(lambda p: setattr(p, "nx", 31))[0] == L.FWI_ERR_INVALID_ARG   # odd nx
+    assert _create_status(lambda p: setattr(p, "nt", 0))[0] == L.FWI_ERR_INVALID_ARG
+    assert _create_status(lambda p: setattr(p, "c_min", -1.0))[0] == L.FWI_ERR_INVALID_ARG
+    assert _create_status(lambda p: setattr(p, "dt", 1e-5))[0] == L.FWI_ERR_INVALID_ARG  # kappa argument too large
+
+    def src_in_pml(g, prob):
+        g["src"][0] = (0, 0, 0)
+    assert _create_status(mutate_geo=src_in_pml)[0] == L.FWI_ERR_INVALID_ARG
+
+    def dup_rec(g, prob):
+        g["rec"][1] = g["rec"][0]
+    assert _create_status(mutate_geo=dup_rec)[0] == L.FWI_ERR_INVALID_ARG
+
+    def bnd_outside(g, prob):
+        g["boundary"][0, 0, 0] = 1
+    assert _create_status(mutate_geo=bnd_outside)[0] == L.FWI_ERR_INVALID_ARG
+
+    def gamma_in_pml(g, prob):
+        g["gamma"][0, :, :] = 1
+    assert _create_status(mutate_geo=gamma_in_pml)[0] == L.FWI_ERR_INVALID_ARG
+
+    def src_in_gamma(g, prob):
+        z, y, x = np.argwhere(prob.gamma)[0]
+        g["src"][0] = (x, y, z)
+    assert _create_status(mutate_geo=src_in_gamma)[0] == L.FWI_ERR_INVALID_ARG

@@ -188,3 +188,57 @@ def test_tuning_is_bit_identical_and_autotune_caches(tmp_path):
     h.tuning = {"y_tile_bytes": 64, "zm_tile_bytes": 64, "zp_tile_bytes": 64}
     assert autotune.apply(h, cache=cache) == choice and h.tuning == choice
     h.close()
+
+
+def test_error_paths():
+    # no tape -> FWI_ERR_NO_TAPE; c outside [c_min, c_max] with check -> INVALID_ARG;
+    # non-finite result with check -> UNSTABLE; the handle stays usable afterwards
+    from paper_2102_00755_amd import _lib as L
+    from paper_2102_00755_amd.fwi import FwiError, Handle, rademacher
+    prob = make_small(shape=(16, 24, 32), nt=20, precision=4)
+    h = Handle.from_problem(prob)
+    S = torch.from_numpy(prob.src_signals())
+    w = torch.from_numpy(rademacher(prob.enc_seed, prob.n_src))
+    c = torch.from_numpy(prob.c_eval)
+    r = torch.from_numpy(random_traces(prob.nt, prob.n_rec, 3, 1e-3))
+    with pytest.raises(FwiError) as e:
+        h.backward(c, r)
+    assert e.value.status == L.FWI_ERR_NO_TAPE
+    bad = c.clone()
+    bad[3, 4, 5] = prob.c_max * 2
+    obs = h.forward(torch.from_numpy(prob.c_true), S, w)[0]
+    with pytest.raises(FwiError) as e:
+        h.gradient(bad, S, w, obs, check=True)
+    assert e.value.status == L.FWI_ERR_INVALID_ARG
+    nan_obs = obs.clone()
+    nan_obs[2, 1] = float("nan")
+    with pytest.raises(FwiError) as e:
+        h.gradient(c, S, w, nan_obs, check=True)
+    assert e.value.status == L.FWI_ERR_UNSTABLE
+    mis, g = h.gradient(c, S, w, obs, check=True)          # still works
+    assert torch.isfinite(g).all() and float(mis[0]) > 0
+    h.forward(c, S, w, save_tape=True)
+    mis_b, g_b = h.backward(c, r, check=True)
+    assert torch.isfinite(g_b).all()
+    h.close()
+
+
+def test_zero_tr_initialisation_suffices_for_the_128_workload():
+    # T8: where the paper starts the TR from zero (the field has left Gamma by
+    # T), the final-state start changes the gradient little
+    from paper_2102_00755_amd.fwi import Handle, rademacher
+    prob = make_config("c128")
+    h = Handle.from_problem(prob, precision=4)
+    S = torch.from_numpy(prob.src_signals())
+    w = torch.from_numpy(rademacher(prob.enc_seed, prob.n_src))
+    obs = h.forward(torch.from_numpy(prob.c_true), S, w)[0]
+    c = torch.from_numpy(prob.c_eval)
+    _, g0 = h.gradient(c, S, w, obs)
+    g0 = g0.clone()
+    h.tr_final_state = True
+    _, g1 = h.gradient(c, S, w, obs)
+    g = prob.gamma.astype(bool)
+    d = rel(g0[0].cpu().numpy()[g], g1[0].cpu().numpy()[g])
+    print("zero vs final-state TR start, rel l2 on Gamma:", d, flush=True)
+    assert d < 0.05
+    h.close()
