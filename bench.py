@@ -68,7 +68,7 @@ def measured_traffic(kernel: str, bytes_per_launch: float):
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4, help="timed TR gradients")
+    ap.add_argument("--steps", type=int, default=5, help="timed TR gradients")
     ap.add_argument("--warmup", type=int, default=1, help="untimed TR gradients")
     ap.add_argument("--config", default="full", help="synth config name (default: the full-size workload)")
     ap.add_argument("--nt", type=int, default=None, help="override the number of time steps")

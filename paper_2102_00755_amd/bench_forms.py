@@ -1,7 +1,7 @@
 """Throughput and latency of the batched and served forms.
 
     python -m paper_2102_00755_amd.bench_forms batched [--batch 16] [--nt 600]
-    python -m paper_2102_00755_amd.bench_forms serve [--requests 60] [--seconds-scale 1]
+    python -m paper_2102_00755_amd.bench_forms serve [--requests 200] [--seconds-scale 1]
     python -m paper_2102_00755_amd.bench_forms lbfgs [--n 4954176] [--m 64]
     python -m paper_2102_00755_amd.bench_forms multigrid
 
@@ -249,7 +249,7 @@ def main():
     ap.add_argument("form", choices=["batched", "serve", "lbfgs", "multigrid"])
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--nt", type=int, default=None)
-    ap.add_argument("--requests", type=int, default=60)
+    ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--inflight", type=int, default=4)
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--n", type=int, default=4954176)
