@@ -19,7 +19,9 @@ the homogeneous Green's function, exact reversibility, linearity,
 finite differences, the dot-product test, published SplitMix64 outputs).
 ``oracle.slbfgs`` holds the stochastic L-BFGS of App. D (Algorithm 2), pinned
 by tests/test_oracle_slbfgs.py; ``oracle.multigrid`` the grid transfers of
-App. C, pinned by tests/test_oracle_multigrid.py.
+App. C, pinned by tests/test_oracle_multigrid.py; ``oracle.lossy`` the
+power-law absorption of Sec. 2.1 (lossy forward, TR with the absorption sign
+switched, exact lossy gradient), pinned by tests/test_oracle_lossy.py.
 
 Parity unpinned: the absolute PML profile and the source pulse shape are
 definitions of this build (the paper gives neither); they are checked only
