@@ -181,6 +181,36 @@ int fwi_get_tuning(const fwi_handle* h, fwi_tuning* out);
  * enqueued).  FWI_ERR_INVALID_ARG (tuning unchanged) for other values. */
 int fwi_set_tuning(fwi_handle* h, const fwi_tuning* t);
 
+/* Power-law absorption and dispersion (Sec. 2.1, the operator L of the
+ * pressure-density relation eq. PreDenRel; Sec. 3.1 for time reversal in
+ * absorbing media).  While set, every simulation of the handle uses
+ *   p = c0^2 (s + tau A[d] - eta B[s]),  s = sum_xi rho_xi,
+ *   d = rho0 sum_xi d-_xi v_xi,  A = F^-1 |k|^{y-2} F,  B = F^-1 |k|^{y-1} F
+ *   (both multipliers 0 at k = 0),
+ *   tau = -2 alpha0 c0^{y-1},  eta = 2 alpha0 c0^y tan(pi y / 2),
+ * in place of p = c0^2 s: fwi_forward, fwi_gradient, fwi_backward and the
+ * batched gradient.  The adjoint simulation uses the same lossy step; the TR
+ * simulation switches the sign of tau when tr_flip != 0 (Sec. 3.1) and keeps
+ * it otherwise; the gradient keeps the form of Alg. 1 (2 / c0^3 times the
+ * second time difference of the TR pressure against the adjoint pressure,
+ * without the dL/dc0 terms of App. A).
+ *   alpha0        Np (rad/s)^-y m^-1 (uniform), >= 0 and finite
+ *   y             power-law exponent, 0 < y < 2, y != 1
+ *   alpha0_field  NULL, or a device array [nz][ny][nx] of the handle's
+ *                 precision holding alpha0 per voxel (then alpha0 is unused
+ *                 except for alpha0 == 0 && alpha0_field == NULL, which
+ *                 switches absorption off); read by every later call, so it
+ *                 must stay allocated while absorption is set (the caller owns it)
+ * The lossy step replaces the fused X2 pass by five launches (density
+ * update, forward y, absorption z pass, inverse y, equation of state) and
+ * runs without step graphs (FWI_GRAPH has no effect); FWI_TR_FINAL_STATE is
+ * rejected with FWI_ERR_INVALID_ARG.  The first call that switches absorption
+ * on allocates batch x |Gamma| values of device memory (FWI_ERR_OOM on
+ * failure).  Any call invalidates the saved tape.  Errors:
+ * FWI_ERR_INVALID_ARG (nothing changed) for a NULL handle, alpha0 < 0 or not
+ * finite, or y outside the range. */
+int fwi_set_absorption(fwi_handle* h, double alpha0, double y, const void* alpha0_field, int32_t tr_flip);
+
 /* Pass kinds of one time step, for fwi_timing_* (one kernel symbol each). */
 enum {
   FWI_PASS_Y_FWD = 0,    /* forward y-FFT                                     */

@@ -29,6 +29,11 @@ template <typename T> hipError_t launch_axis_zp(int L, int tb, dim3 grid, hipStr
 template <typename T> hipError_t launch_axis_ys(int L, int tb, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
 template <typename T>
 hipError_t launch_axis_yv(int L, int part, int tb, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
+// absorption z pass (k_axis_z_frac)
+template <typename T> hipError_t launch_axis_zf(int L, int tb, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
+// lossy x passes: part 0 = k_x_lossy_rho, part 1 = k_x_lossy_eos; kind = SpKind
+template <typename T>
+hipError_t launch_x_lossy(int M, int part, int kind, dim3 grid, hipStream_t st, const X2Args<T>& a);
 template <typename T> hipError_t launch_x_vel(int M, dim3 grid, hipStream_t st, const XArgs<T>& a);
 template <typename T> hipError_t launch_x_den(int M, int mode, dim3 grid, hipStream_t st, const X2Args<T>& a);
 template <typename T> hipError_t launch_x_r2c(int M, dim3 grid, hipStream_t st, const XArgs<T>& a, const T* in, int f);

@@ -303,6 +303,8 @@ struct EngineBase {
   virtual int backward(int B, const void* c, const void* resid, double* misfit, void* grad, int flags,
                        hipStream_t st) = 0;
   virtual int derivative(const void* in, void* out, int axis, int sign, hipStream_t st) = 0;
+  // power-law absorption (Sec. 2.1); alpha0 == 0 with no field switches it off
+  virtual int set_absorption(double alpha0, double y, const void* field, int tr_flip) = 0;
   // Gamma-compact vectors: compact[k] = full[gamma voxel k] (gather) or back
   virtual int gamma_copy(const void* src, void* dst, bool gather, hipStream_t st) = 0;
   virtual long long gamma_count() const = 0;
@@ -345,6 +347,13 @@ template <typename T> struct Engine : EngineBase {
   bool tape_valid = false;
   int tape_B = 0;
   T scale = 0, kap_a = 0;
+  // absorption (set_absorption): the lossy passes replace X2 while set
+  bool lossy = false;
+  double a0u = 0.0, ypow = 1.5;
+  const T* a0f = nullptr;
+  bool tr_flip = true;
+  DevBuf mem_padj;
+  T* padj = nullptr;
 
   int init(const fwi_params& prm, Geometry&& g, int dev) {
     p = prm;
@@ -521,6 +530,8 @@ template <typename T> struct Engine : EngineBase {
     a.slots = slot_table; a.slot0 = slot0; a.na = na; a.slot1 = slot1; a.nf = nf; a.f0 = f0;
     a.d = d; a.tb = tb; a.scale = scale; a.kap_a = kap_a;
     a.vcoef = (T)((double)p.nx * p.dt / p.rho0);
+    a.half_e0 = (T)((ypow - 1.0) / 2.0);
+    a.half_e1 = (T)((ypow - 2.0) / 2.0);
     return a;
   }
   // tiles per spectrum row of an axis pass of kind k (AxisKind)
@@ -598,6 +609,112 @@ template <typename T> struct Engine : EngineBase {
       const double b = B * (2 * (4 * S + 6 * F) + F + t * (d.n_rec + d.n_bnd + 3.0 * d.n_gam) + 16.0 * d.n_gam);
       timer.end(ev, FWI_PASS_X_DEN_PAIR, b, st);
     }
+    return FWI_OK;
+  }
+
+  // --- lossy passes (absorption) -------------------------------------------
+  void lossy_args(X2Args<T>& a) const {
+    a.rho0 = (T)p.rho0;
+    a.alpha0 = a0f;
+    a.alpha0_u = (T)a0u;
+    a.y1 = (T)(ypow - 1.0);
+    a.two_tan = (T)(2.0 * std::tan(kPi * ypow / 2.0));
+    a.tr_tau_sign = tr_flip ? (T)-1 : (T)1;
+    a.padj = padj;
+  }
+  // density update, fractional Laplacians and equation of state of the
+  // simulations of kind k0 (and k1 >= 0 in the same launches of the axis
+  // passes): XL1, forward y, absorption z, inverse y, XL2
+  int lossy_eos(int B, int k0, int k1, const X2Args<T>& a, hipStream_t st) {
+    const int lpb = x_lines_per_block_den<T>(d.M);
+    const dim3 gx((d.nlines + lpb - 1) / lpb, B);
+    FWI_HIP(launch_x_lossy<T>(d.M, 0, k0, gx, st, a));
+    if (k1 >= 0) FWI_HIP(launch_x_lossy<T>(d.M, 0, k1, gx, st, a));
+    const int s0 = (k0 == SP_ADJOINT) ? 0 : p.batch;
+    const int s1 = (k1 < 0) ? s0 : ((k1 == SP_ADJOINT) ? 0 : p.batch);
+    const int ns = (k1 < 0) ? B : 2 * B;
+    const int ty = tile_bytes[AK_Y], tz = tile_bytes[AK_ZMINUS];
+    const AxisArgs<T> ax = axis_args(s0, B, s1, 2, 0);
+    FWI_HIP(launch_axis_y<T>(d.ny, false, ty, dim3(ntx(AK_Y) * d.nz, ns * 2), st, ax));
+    FWI_HIP(launch_axis_zf<T>(d.nz, tz, dim3(ntx(AK_ZMINUS) * d.ny, ns * 2), st, ax));
+    FWI_HIP(launch_axis_y<T>(d.ny, true, ty, dim3(ntx(AK_Y) * d.nz, ns * 2), st, ax));
+    FWI_HIP(launch_x_lossy<T>(d.M, 1, k0, gx, st, a));
+    if (k1 >= 0) FWI_HIP(launch_x_lossy<T>(d.M, 1, k1, gx, st, a));
+    return FWI_OK;
+  }
+  int lossy_grad(int B, const T* c, const X2Args<T>& a, bool adj_only, hipStream_t st) {
+    if (d.n_gam == 0) return FWI_OK;
+    const int blocks = (int)std::min<long long>((d.n_gam + 255) / 256, 4096);
+    hipLaunchKernelGGL((k_lossy_grad<T>), dim3(blocks, B), dim3(256), 0, st, c, gam_lin, padj, ring, gacc,
+                       (int)d.n_gam, (long long)d.nfield, a.ring_a, a.ring_b, a.ring_c, adj_only ? 1 : 0);
+    FWI_HIP(hipGetLastError());
+    return FWI_OK;
+  }
+  // Alg. 1 setup after the residual and the interleaved iterations, lossy:
+  // the TR switches the sign of tau (unless tr_flip is off) and starts from
+  // the tape only; gradient in the lossless form (2 / c0^3, ring of p_tr)
+  int lossy_adjoint_tr(int B, const T* c, hipStream_t st) {
+    const int N = p.nt, tr0 = p.batch;
+    int rc;
+    X2Args<T> a = x2_args(B, c);
+    lossy_args(a);
+    a.adj_src = adj; a.tape = tape;
+    for (int b = 0; b < B; ++b)
+      if ((rc = zero_velocity(tr0 + b, st))) return rc;
+    a.tr_state_mode = 1; a.tape_row = N - 1; a.ring_c = 0; a.step = 0;
+    if ((rc = lossy_eos(B, SP_DIRICHLET, -1, a, st))) return rc;
+    a.tr_state_mode = 0;
+    if (N == 1) {  // p_tr^(1) = 0
+      if ((rc = fill<T>(ring, (long long)B * 3 * d.n_gam, (T)0, st))) return rc;
+    }
+    if (N >= 2) {  // advance the TR by one step to get ahead of the adjoint
+      if ((rc = step_spectral(tr0, B, tr0, B, st))) return rc;
+      a.tape_row = N - 2; a.ring_c = 1;
+      if ((rc = lossy_eos(B, SP_DIRICHLET, -1, a, st))) return rc;
+    }
+    for (int j = 0; j < N; ++j) {
+      const int k = j + 2;
+      a.step = j;
+      a.ring_a = j % 3; a.ring_b = (j + 1) % 3; a.ring_c = k % 3;
+      if (k <= N - 1) {
+        if ((rc = step_spectral(0, B, tr0, 2 * B, st))) return rc;
+        a.tape_row = N - 1 - k;
+        if ((rc = lossy_eos(B, SP_ADJOINT, SP_DIRICHLET, a, st))) return rc;
+        if ((rc = lossy_grad(B, c, a, false, st))) return rc;
+      } else {
+        if ((rc = step_spectral(0, B, 0, B, st))) return rc;
+        if ((rc = lossy_eos(B, SP_ADJOINT, -1, a, st))) return rc;
+        if ((rc = lossy_grad(B, c, a, true, st))) return rc;
+      }
+    }
+    return FWI_OK;
+  }
+
+  int set_absorption(double alpha0, double y, const void* field, int flip) override {
+    if (!std::isfinite(alpha0) || alpha0 < 0.0) return fail(FWI_ERR_INVALID_ARG, "alpha0 must be finite and >= 0");
+    tape_valid = false;
+    if (alpha0 == 0.0 && !field) {
+      lossy = false;
+      a0f = nullptr;
+      a0u = 0.0;
+      return FWI_OK;
+    }
+    if (!(y > 0.0 && y < 2.0) || y == 1.0)
+      return fail(FWI_ERR_INVALID_ARG, "power-law exponent y must lie in (0, 2) and differ from 1");
+    if (!mem_padj.p) {
+      FWI_HIP(hipSetDevice(device));
+      const size_t n = std::max<size_t>((size_t)p.batch * std::max<long long>(d.n_gam, 1) * sizeof(T), 256);
+      if (hipMalloc(&mem_padj.p, n) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(FWI_ERR_OOM, "device allocation of " + std::to_string(n) + " bytes failed");
+      }
+      padj = (T*)mem_padj.p;
+    }
+    lossy = true;
+    a0u = alpha0;
+    a0f = (const T*)field;
+    ypow = y;
+    tr_flip = flip != 0;
     return FWI_OK;
   }
 
@@ -686,6 +803,15 @@ template <typename T> struct Engine : EngineBase {
     if ((rc = zero_slots(tr0, B, st))) return rc;   // p^0 = 0, v = 0, rho = 0
     X2Args<T> a = x2_args(B, c);
     a.src_sig = src; a.w = w; a.traces = traces; a.tape = save ? tape : nullptr;
+    if (lossy) {   // eager launches (no step graph)
+      lossy_args(a);
+      for (int n = 0; n < p.nt; ++n) {
+        if ((rc = step_spectral(tr0, B, tr0, B, st))) return rc;
+        a.step = n;
+        if ((rc = lossy_eos(B, SP_SOURCE, -1, a, st))) return rc;
+      }
+      return FWI_OK;
+    }
     if (use_graph) {
       if ((rc = fill<int>(step_counter, 1, 0, st))) return rc;
       a.step_dev = step_counter;
@@ -718,6 +844,11 @@ template <typename T> struct Engine : EngineBase {
     FWI_HIP(hipGetLastError());
     if ((rc = fill<double>(gacc, (long long)B * d.n_gam, 0.0, st))) return rc;
     if ((rc = zero_slots(0, B, st))) return rc;           // adjoint state
+    if (lossy) {
+      if (final_state) return fail(FWI_ERR_INVALID_ARG, "FWI_TR_FINAL_STATE is not available with absorption");
+      if ((rc = lossy_adjoint_tr(B, c, st))) return rc;
+      return scatter_grad(B, grad, st);
+    }
     X2Args<T> a = x2_args(B, c);
     a.adj_src = adj; a.tape = tape;
     // TR initial state: zero interior (or the final forward state), dGamma <- g^{N-1}
@@ -777,7 +908,11 @@ template <typename T> struct Engine : EngineBase {
       }
     }
     timer.active = false;
-    // G on Gamma -> full grid, zero elsewhere
+    return scatter_grad(B, grad, st);
+  }
+  // G on Gamma -> full grid, zero elsewhere
+  int scatter_grad(int B, T* grad, hipStream_t st) {
+    int rc;
     if ((rc = fill<T>(grad, (long long)B * d.nfield, (T)0, st))) return rc;
     if (d.n_gam > 0) {
       hipLaunchKernelGGL((k_grad_scatter<T>), dim3((d.n_gam + 255) / 256, B), dim3(256), 0, st, gacc, gam_lin,
@@ -1089,6 +1224,11 @@ int fwi_backward(fwi_handle* h, int32_t B, const void* c, const void* residual, 
 int fwi_derivative(fwi_handle* h, const void* in, void* out, int32_t axis, int32_t sign, fwi_stream_t stream) {
   if (!h) return fail(FWI_ERR_INVALID_ARG, "handle is NULL");
   return h->eng->derivative(in, out, axis, sign, (hipStream_t)stream);
+}
+
+int fwi_set_absorption(fwi_handle* h, double alpha0, double y, const void* alpha0_field, int32_t tr_flip) {
+  if (!h) return fail(FWI_ERR_INVALID_ARG, "handle is NULL");
+  return h->eng->set_absorption(alpha0, y, alpha0_field, tr_flip);
 }
 
 int fwi_get_tuning(const fwi_handle* h, fwi_tuning* out) {

@@ -126,6 +126,8 @@ template <typename T> struct AxisArgs {
   T scale;     // 1 / (nx ny nz)
   T kap_a;     // (c_ref dt / 2)^2
   T vcoef;     // nx dt / rho0: velocity update of the x-spectrum states
+  T half_e0;   // absorption pass: |k|^{2 half_e0} on field 0 (B[s]: (y - 1) / 2)
+  T half_e1;   //                  |k|^{2 half_e1} on field 1 (A[d]: (y - 2) / 2)
 };
 
 __device__ __forceinline__ int slot_of(int i, int slot0, int na, int slot1) {
@@ -381,6 +383,59 @@ k_axis_z_plus(AxisArgs<T> a) {
   __syncthreads();
   lds_fft<T, L, TW, TW, NT, true>(buf, twl);
   tile_store<T, L, TW, NT>(buf, s2 + off, rstride, ncol);
+}
+
+// x^e for x > 0 in the kernel's precision
+__device__ __forceinline__ float real_pow(float x, float e) { return powf(x, e); }
+__device__ __forceinline__ double real_pow(double x, double e) { return pow(x, e); }
+
+// Z pass of the absorption operators (Sec. 2.1, the fractional Laplacians of
+// L): field f -> F_z^-1 m_f F_z field f with the radial multiplier
+// m_f = |k|^{2 e_f} / (nx ny nz), |k|^2 = kx^2 + ky^2 + kz^2, and m_f = 0 at
+// k = 0: e_0 = (y - 1) / 2 for s (field 0), e_1 = (y - 2) / 2 for d (field 1).
+// L == nz.
+template <typename T, int L, int TB>
+__global__ void __launch_bounds__(axis_nt(L, tile_tw<T, TB>()))
+k_axis_z_frac(AxisArgs<T> a) {
+  using C = cplx<T>;
+  constexpr int TW = tile_tw<T, TB>();
+  constexpr int NT = axis_nt(L, TW);
+  constexpr int EPT = (L * TW + NT - 1) / NT;
+  static_assert(NT % TW == 0, "z tile: NT must be a multiple of TW");
+  __shared__ C buf[L * TW];
+  __shared__ C twl[L];
+  const int ntx = (a.d.px + TW - 1) / TW;   // tiles per spectrum row
+  const int tile = blockIdx.x % ntx;
+  const int y = blockIdx.x / ntx;
+  const int s = slot_of(blockIdx.y / a.nf, a.slot0, a.na, a.slot1);
+  const int f = a.f0 + blockIdx.y % a.nf;
+  const size_t px = a.d.px;
+  const size_t rstride = (size_t)a.d.ny * px;
+  C* g = a.slots[s].spec[f] + (size_t)y * px + (size_t)tile * TW;
+  const int ncol = min(TW, (int)px - tile * TW);
+  const int kx = min(tile * TW + (int)threadIdx.x % TW, a.d.M);
+  const T he = (f == 0) ? a.half_e0 : a.half_e1;
+  const T base = a.tb.ksq[0][kx] + a.tb.ksq[1][y];
+  T m[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int r = (int)threadIdx.x / TW + i * (NT / TW);
+    if ((L * TW) % NT == 0 || r < L) {
+      const T q = base + a.tb.ksq[2][r];
+      m[i] = q > (T)0 ? real_pow(q, he) * a.scale : (T)0;
+    }
+  }
+  tile_load<T, L, TW, NT>(buf, g, rstride, ncol, twl, a.tb.tw_z);
+  __syncthreads();
+  lds_fft<T, L, TW, TW, NT, false>(buf, twl);
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = (int)threadIdx.x + i * NT;
+    if ((L * TW) % NT == 0 || e < L * TW) buf[e] = cscale(buf[e], m[i]);
+  }
+  __syncthreads();
+  lds_fft<T, L, TW, TW, NT, true>(buf, twl);
+  tile_store<T, L, TW, NT>(buf, g, rstride, ncol);
 }
 
 // Inverse y pass after Z2: per slot, part 0 reads Q (field 0) and writes
@@ -820,6 +875,14 @@ template <typename T> struct X2Args {
   // When non-null the step index is read from device memory (replayed graph
   // of one time step); tape row and ring slots then follow from it.
   const int* step_dev;
+  // absorption (lossy passes only)
+  T rho0;
+  const T* alpha0;       // [nfield] per-voxel alpha0 or null (then alpha0_u)
+  T alpha0_u;            // uniform alpha0, Np (rad/s)^-y m^-1
+  T y1;                  // y - 1
+  T two_tan;             // 2 tan(pi y / 2)
+  T tr_tau_sign;         // sign of tau in the TR simulation (-1: switched)
+  T* padj;               // [B][n_gam]: adjoint pressure on Gamma of this step
 };
 
 // Per-launch step indices of an X2 launch.
@@ -865,7 +928,11 @@ __device__ __forceinline__ int local_line(const int32_t* off, int l0, int nl, in
 // only), 2 = keep the stored densities (TR start from the final forward state)
 // STAGE_TW: this call also stages the x twiddles in twl (the first call of
 // the workgroup); later calls find them there.
-template <typename T, int M, int LPB, int TWP, int TWPP, int KIND, bool STAGE_TW>
+// LOSSY: instead of p, column pcol receives s = sum_a rho_a and column
+// pcol + LPB receives d = rho0 sum_a d-_a v_a (0 without a density step), and
+// s is also stored as a real field in the slot's third spectrum buffer (rows
+// of px complex), for the lossy equation of state.
+template <typename T, int M, int LPB, int TWP, int TWPP, int KIND, bool STAGE_TW, bool LOSSY = false>
 __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx& si, const Slot<T>& sl, int b,
                                                int l0, int nl, int state_mode, int pcol, cplx<T>* buf,
                                                cplx<T>* bufp, cplx<T>* spv, uint8_t* spm, cplx<T>* twl) {
@@ -884,7 +951,7 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx
   lanes2d_all<LPB, M>([&](int i, int l, int n, bool) {
     const int line = l0 + min(l, nl - 1);
     const size_t lo = (size_t)line * nx;
-    cc[i] = gld(reinterpret_cast<const C*>(cb + lo) + n);
+    if (!LOSSY) cc[i] = gld(reinterpret_cast<const C*>(cb + lo) + n);
     if (!zero_state) {
 #pragma unroll
       for (int f = 0; f < 3; ++f) rr[i][f] = gld(reinterpret_cast<const C*>(sl.rho[f] + lo) + n);
@@ -955,6 +1022,7 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx
     const C c2 = cc[i];
     const C sv = spv[n * LPB + l];
     C sum = cmake<C>((T)0, (T)0);
+    C dsum = cmake<C>((T)0, (T)0);
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
       C* rp = reinterpret_cast<C*>(sl.rho[f] + (size_t)line * nx) + n;
@@ -965,6 +1033,7 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx
         rn = rr[i][f];
       } else {
         const C dv = buf[n * TWP + f * LPB + l];
+        if (LOSSY) dsum = cadd(dsum, dv);
         const T lx = f == 0 ? l0f[i].x : (f == 1 ? l1f[i] : l2f[i]);
         const T ly = f == 0 ? l0f[i].y : (f == 1 ? l1f[i] : l2f[i]);
         rn = cmake<C>(lx * (lx * rr[i][f].x - a.dt_rho0 * dv.x), ly * (ly * rr[i][f].y - a.dt_rho0 * dv.y));
@@ -978,7 +1047,13 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx
       gst(rp, rn);
       sum = cadd(sum, rn);
     }
-    bufp[n * TWPP + pcol + l] = cmake<C>(c2.x * c2.x * sum.x, c2.y * c2.y * sum.y);
+    if (LOSSY) {
+      bufp[n * TWPP + pcol + l] = sum;
+      bufp[n * TWPP + pcol + LPB + l] = cmake<C>(a.rho0 * dsum.x, a.rho0 * dsum.y);
+      gst(sl.spec[2] + (size_t)line * px + n, sum);
+    } else {
+      bufp[n * TWPP + pcol + l] = cmake<C>(c2.x * c2.x * sum.x, c2.y * c2.y * sum.y);
+    }
   });
   __syncthreads();
 }
@@ -1081,6 +1156,154 @@ __global__ void __launch_bounds__(X_NT) k_x_density(X2Args<T> a) {
   } else {
     cplx<T>* specs[1] = {(MODE == XM_TRONLY || MODE == XM_FWD) ? s_tr.spec[0] : s_adj.spec[0]};
     x_store_spectra<T, M, LPB, TWPP, 1>(bufp, specs, 0, l0, nl, px);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// lossy passes (power-law absorption, Sec. 2.1): the density update is split
+// from the equation of state, which needs the fractional Laplacians of s and d
+// (three axis passes in between: forward y, k_axis_z_frac, inverse y)
+// ----------------------------------------------------------------------------
+// XL1: C2R of d-_a v_a, split-density update with PML and the injection or
+// imposition of KIND (SP_SOURCE forward, SP_ADJOINT adjoint, SP_DIRICHLET TR
+// with a.tr_state_mode as in X2), then s = sum_a rho_a (also kept as a real
+// field in the third spectrum buffer) and d = rho0 sum_a d-_a v_a, whose
+// forward x transforms go to fields 0 (s) and 1 (d).
+template <typename T, int M, int KIND>
+__global__ void __launch_bounds__(X_NT) k_x_lossy_rho(X2Args<T> a) {
+  using C = cplx<T>;
+  constexpr int LPB = x_lpb_den<T>(M);
+  constexpr int TWP = 3 * LPB;        // d-_a v_a of the three axes
+  constexpr int TWPP = 2 * LPB;       // s and d
+  __shared__ C buf[(M + 1) * TWP];
+  __shared__ C bufp[(M + 1) * TWPP];
+  __shared__ C spv[M * LPB];
+  __shared__ uint8_t spm[KIND == SP_DIRICHLET ? 2 * M * LPB : 1];
+  __shared__ C twl[XTw<M>::N];
+  const int l0 = blockIdx.x * LPB;
+  const int nl = min(LPB, a.d.nlines - l0);
+  const int b = blockIdx.y;
+  const Slot<T> sl = a.slots[KIND == SP_ADJOINT ? b : a.tr_off + b];
+  const StepIdx si{a.step, a.tape_row, a.ring_a, a.ring_b, a.ring_c};
+  const int state_mode = KIND == SP_DIRICHLET ? a.tr_state_mode : 0;
+  density_update<T, M, LPB, TWP, TWPP, KIND, true, true>(a, si, sl, b, l0, nl, state_mode, 0, buf, bufp, spv,
+                                                         spm, twl);
+  lds_fft<T, M, TWPP, TWPP, X_NT, false>(bufp, twl);
+  r2c_post<T, M, TWPP, TWPP>(bufp, twl + M);
+  __syncthreads();
+  cplx<T>* specs[2] = {sl.spec[0], sl.spec[1]};
+  x_store_spectra<T, M, LPB, TWPP, 2>(bufp, specs, 0, l0, nl, a.d.px);
+}
+
+// XL2: C2R of fields 0 (B[s] = F^-1 |k|^{y-1} F s) and 1 (A[d] =
+// F^-1 |k|^{y-2} F d), lossy equation of state
+//   p = c0^2 (s + sgn tau A[d] - eta B[s]),
+//   tau = -2 alpha0 c0^{y-1},  eta = 2 alpha0 c0^y tan(pi y / 2),
+// sgn = a.tr_tau_sign for the TR (KIND SP_DIRICHLET), else +1; then the
+// outputs of KIND (forward: traces f^n and tape g^n; adjoint: p on Gamma to
+// a.padj; TR: p on Gamma to ring slot a.ring_c) and the forward x transform
+// of p into field 0.
+template <typename T, int M, int KIND>
+__global__ void __launch_bounds__(X_NT) k_x_lossy_eos(X2Args<T> a) {
+  using C = cplx<T>;
+  constexpr int LPB = x_lpb_den<T>(M);
+  constexpr int TWP = 2 * LPB;        // B[s] in columns 0.., A[d] in LPB..
+  __shared__ C buf[(M + 1) * TWP];
+  __shared__ C twl[XTw<M>::N];
+  const int l0 = blockIdx.x * LPB;
+  const int nl = min(LPB, a.d.nlines - l0);
+  const int b = blockIdx.y;
+  const int nx = a.d.nx;
+  const size_t px = a.d.px;
+  const Slot<T> sl = a.slots[KIND == SP_ADJOINT ? b : a.tr_off + b];
+  const T* cb = a.c + (size_t)b * a.d.nfield;
+  const T sgn = KIND == SP_DIRICHLET ? a.tr_tau_sign : (T)1;
+  using Ly = Lanes<LPB, M>;
+  C ss[Ly::NI], cc[Ly::NI], aa[Ly::NI];
+  lanes2d_all<LPB, M>([&](int i, int l, int n, bool) {
+    const int line = l0 + min(l, nl - 1);
+    ss[i] = gld(sl.spec[2] + (size_t)line * px + n);
+    cc[i] = gld(reinterpret_cast<const C*>(cb + (size_t)line * nx) + n);
+    aa[i] = a.alpha0 ? gld(reinterpret_cast<const C*>(a.alpha0 + (size_t)line * nx) + n)
+                     : cmake<C>(a.alpha0_u, a.alpha0_u);
+  });
+  {
+    C pre[SpecRegs<T, M, LPB, 2>::N], tt[XTw<M>::PER];
+    x_prefetch_spectra<T, M, LPB, 2>(pre, sl.spec, l0, nl, px);
+    x_tw_prefetch<T, M>(tt, a.tb);
+    x_commit_spectra<T, M, LPB, TWP, 2>(buf, pre, 0);
+    x_tw_commit<T, M>(twl, tt);
+  }
+  __syncthreads();
+  c2r_pre<T, M, TWP, TWP>(buf, twl + M);
+  __syncthreads();
+  lds_fft<T, M, TWP, TWP, X_NT, true>(buf, twl);
+  auto eos = [&](T s, T A, T B, T c, T al) -> T {
+    const T cy1 = real_pow(c, a.y1);               // c0^{y-1}
+    const T tau = (T)-2 * al * cy1;
+    const T eta = a.two_tan * al * (c * cy1);
+    return c * c * (s + sgn * tau * A - eta * B);
+  };
+  lanes2d<LPB, M>([&](int i, int l, int n) {
+    if (l >= nl) return;
+    const C Bv = buf[n * TWP + l];
+    const C Av = buf[n * TWP + LPB + l];
+    buf[n * TWP + l] = cmake<C>(eos(ss[i].x, Av.x, Bv.x, cc[i].x, aa[i].x), eos(ss[i].y, Av.y, Bv.y, cc[i].y, aa[i].y));
+  });
+  __syncthreads();
+  if (KIND == SP_SOURCE) {
+    const int i0 = a.g.rec_off[l0], i1 = a.g.rec_off[l0 + nl];
+    for (int i = i0 + (int)threadIdx.x; i < i1; i += X_NT) {
+      const int l = local_line(a.g.rec_off, l0, nl, i);
+      a.traces[((size_t)b * a.d.nt + a.step) * a.d.n_rec + a.g.rec_id[i]] = p_at<T, TWP>(buf, 0, l, a.g.rec_x[i]);
+    }
+    if (a.tape) {
+      const int j0 = a.g.bnd_off[l0], j1 = a.g.bnd_off[l0 + nl];
+      T* trow = a.tape + ((size_t)b * a.d.nt + a.step) * a.d.n_bnd;
+      for (int i = j0 + (int)threadIdx.x; i < j1; i += X_NT) {
+        const int l = local_line(a.g.bnd_off, l0, nl, i);
+        trow[i] = p_at<T, TWP>(buf, 0, l, a.g.bnd_x[i]);
+      }
+    }
+  } else {
+    T* dst = KIND == SP_ADJOINT ? a.padj + (size_t)b * a.d.n_gam
+                                : a.ring + ((size_t)b * 3 + a.ring_c) * a.d.n_gam;
+    const int i0 = a.g.gam_off[l0], i1 = a.g.gam_off[l0 + nl];
+    for (int i = i0 + (int)threadIdx.x; i < i1; i += X_NT) {
+      const int l = local_line(a.g.gam_off, l0, nl, i);
+      dst[i] = p_at<T, TWP>(buf, 0, l, a.g.gam_x[i]);
+    }
+  }
+  __syncthreads();
+  lds_fft<T, M, LPB, TWP, X_NT, false>(buf, twl);
+  r2c_post<T, M, TWP, LPB>(buf, twl + M);
+  __syncthreads();
+  cplx<T>* specs[1] = {sl.spec[0]};
+  x_store_spectra<T, M, LPB, TWP, 1>(buf, specs, 0, l0, nl, px);
+}
+
+// Gradient step of the lossy TR gradient (Alg. 1 form):
+//   G += 2 / c0^3 p_adj (p_tr^(j) - 2 p_tr^(j+1) + p_tr^(j+2))
+// with p_tr^(j+2) = 0 (and that ring slot cleared) when adj_only.
+// grid: x over Gamma voxels, y over problems.
+template <typename T>
+__global__ void k_lossy_grad(const T* c, const int32_t* gam_lin, const T* padj, T* ring, double* gacc, int n_gam,
+                             long long nfield, int ra, int rb, int rc, int adj_only) {
+  const int b = blockIdx.y;
+  T* rg = ring + (size_t)b * 3 * n_gam;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_gam; i += gridDim.x * blockDim.x) {
+    T ptr;
+    if (adj_only) {
+      ptr = (T)0;
+      rg[(size_t)rc * n_gam + i] = ptr;
+    } else {
+      ptr = rg[(size_t)rc * n_gam + i];
+    }
+    const T cv = c[(size_t)b * nfield + gam_lin[i]];
+    const T pm = rg[(size_t)ra * n_gam + i];
+    const T p0 = rg[(size_t)rb * n_gam + i];
+    const T inc = (T)2 / (cv * cv * cv) * padj[(size_t)b * n_gam + i] * (pm - (T)2 * p0 + ptr);
+    gacc[(size_t)b * n_gam + i] += (double)inc;
   }
 }
 

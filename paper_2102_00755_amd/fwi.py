@@ -244,6 +244,22 @@ class Handle:
         t = L.FwiTuning(int(cur["y_tile_bytes"]), int(cur["zm_tile_bytes"]), int(cur["zp_tile_bytes"]))
         _check(self._lib.fwi_set_tuning(self._h, ctypes.byref(t)), "fwi_set_tuning")
 
+    def set_absorption(self, alpha0=0.0, y=1.5, field=None, tr_flip=True) -> None:
+        """Power-law absorption (Sec. 2.1): alpha0 in Np (rad/s)^-y m^-1, either a
+        number or a per-voxel field [nz, ny, nx] (kept on the device by the handle
+        for as long as absorption is set); alpha0 = 0 with no field switches it
+        off.  tr_flip: the TR simulation switches the sign of tau (Sec. 3.1)."""
+        ptr = None
+        self._alpha0_field = None
+        if field is not None:
+            f = self._t(field, self.shape)[0].contiguous()
+            self._alpha0_field = f
+            ptr = ctypes.c_void_p(f.data_ptr())
+        torch.cuda.synchronize(self.device)
+        _check(self._lib.fwi_set_absorption(self._h, float(alpha0), float(y), ptr, 1 if tr_flip else 0),
+               "fwi_set_absorption")
+        self.tape_token += 1
+
     def timing_enable(self, every: int) -> None:
         """Sample every `every`-th time step's pass launches with HIP events."""
         _check(self._lib.fwi_timing_enable(self._h, int(every)), "fwi_timing_enable")
