@@ -4,6 +4,7 @@
     python -m paper_2102_00755_amd.bench_forms serve [--requests 200] [--seconds-scale 1]
     python -m paper_2102_00755_amd.bench_forms lbfgs [--n 4954176] [--m 64]
     python -m paper_2102_00755_amd.bench_forms multigrid
+    python -m paper_2102_00755_amd.bench_forms lossy [--steps 2] [--nt 2200]
 
 batched : 16 independent Rademacher-encoded TR gradients on 128^3 (phantom
           seeds 300..315, encoding seeds 1300..1315), run (a) one after
@@ -19,6 +20,10 @@ serve   : Poisson-arriving forward / gradient requests (50/50) over the grid
 lbfgs   : the SLBFGS two-loop recursion (64 pairs) and pair push at |Gamma| of
           the full workload, with their algorithmic bandwidth.
 multigrid: grid transfers between the 1 mm and 0.5 mm levels of the full box.
+lossy   : the encoded TR gradient of the full workload (448x448x224, 2200
+          steps) with power-law absorption (0.75 dB MHz^-1.5 cm^-1, y = 1.5,
+          TR with the sign of tau switched) against the same gradient without
+          absorption on the same handle.
 Prints one JSON line per run.  Inputs are synthetic (synth/).
 """
 
@@ -244,9 +249,44 @@ def multigrid(args) -> dict:
             "constant_preserved": ok}
 
 
+def lossy(args) -> dict:
+    from synth import make_config
+    prob = make_config("full", nt=args.nt)
+    h = fwi.Handle.from_problem(prob, precision=4)
+    dev = h.device
+    c_eval, c_true, S, w = (t.to(dev) for t in _gradient_inputs(prob, dev, torch.float32))
+    grad = torch.empty((1, *h.shape), device=dev, dtype=torch.float32)
+    work = 3.0 * prob.n_cells * prob.nt
+    out = {"form": "lossy", "workload": "448x448x224, %d steps, 32 encoded emitters, 1024 receivers" % prob.nt,
+           "alpha_db_MHz_cm": 0.75, "y": 1.5}
+    for name, a_db in (("lossy", 0.75), ("lossless", 0.0)):
+        h.set_absorption(fwi.db_to_neper(a_db, 1.5), 1.5)
+        obs = h.forward(c_true, S, w)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h.forward(c_true, S, w)
+        torch.cuda.synchronize()
+        t_fwd = time.perf_counter() - t0
+        h.gradient(c_eval, S, w, obs, out=grad)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            h.gradient(c_eval, S, w, obs, out=grad)
+        torch.cuda.synchronize()
+        t_grad = (time.perf_counter() - t0) / args.steps
+        out[name] = {"gradient_s": t_grad, "Mcell_steps_per_s": work / t_grad / 1e6,
+                     "forward_Mcell_steps_per_s": prob.n_cells * prob.nt / t_fwd / 1e6,
+                     "grad_finite": bool(torch.isfinite(grad).all())}
+        print(json.dumps({name: out[name]}), flush=True)
+    h.close()
+    out["lossy_over_lossless"] = out["lossy"]["gradient_s"] / out["lossless"]["gradient_s"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("form", choices=["batched", "serve", "lbfgs", "multigrid"])
+    ap.add_argument("form", choices=["batched", "serve", "lbfgs", "multigrid", "lossy"])
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--nt", type=int, default=None)
     ap.add_argument("--requests", type=int, default=200)
@@ -255,7 +295,8 @@ def main():
     ap.add_argument("--n", type=int, default=4954176)
     ap.add_argument("--m", type=int, default=64)
     args = ap.parse_args()
-    res = {"batched": batched, "serve": serve, "lbfgs": lbfgs, "multigrid": multigrid}[args.form](args)
+    res = {"batched": batched, "serve": serve, "lbfgs": lbfgs, "multigrid": multigrid,
+           "lossy": lossy}[args.form](args)
     print(json.dumps(res), flush=True)
 
 

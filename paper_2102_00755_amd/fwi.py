@@ -8,6 +8,7 @@ Functions take and return torch tensors on the handle's device.
 from __future__ import annotations
 
 import ctypes
+import math
 from typing import Optional, Sequence, Tuple
 
 import numpy as np
@@ -28,6 +29,12 @@ class FwiError(RuntimeError):
 def _check(status: int, where: str) -> None:
     if status != L.FWI_OK:
         raise FwiError(status, where)
+
+
+def db_to_neper(alpha_db: float, y: float) -> float:
+    """Absorption prefactor in dB MHz^-y cm^-1 -> Np (rad/s)^-y m^-1 (the unit
+    of alpha0 in fwi_set_absorption): 1 dB = ln(10)/20 Np, omega = 2 pi f."""
+    return alpha_db * 100.0 * math.log(10.0) / 20.0 / (2.0 * math.pi * 1.0e6) ** y
 
 
 def rademacher(seed: int, n: int) -> np.ndarray:
