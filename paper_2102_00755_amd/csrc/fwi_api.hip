@@ -638,8 +638,10 @@ template <typename T> struct Engine : EngineBase {
     FWI_HIP(launch_axis_y<T>(d.ny, false, ty, dim3(ntx(AK_Y) * d.nz, ns * 2), st, ax));
     FWI_HIP(launch_axis_zf<T>(d.nz, tz, dim3(ntx(AK_ZMINUS) * d.ny, ns * 2), st, ax));
     FWI_HIP(launch_axis_y<T>(d.ny, true, ty, dim3(ntx(AK_Y) * d.nz, ns * 2), st, ax));
-    FWI_HIP(launch_x_lossy<T>(d.M, 1, k0, gx, st, a));
-    if (k1 >= 0) FWI_HIP(launch_x_lossy<T>(d.M, 1, k1, gx, st, a));
+    const int lpe = x_lines_per_block_eos<T>(d.M);
+    const dim3 ge((d.nlines + lpe - 1) / lpe, B);
+    FWI_HIP(launch_x_lossy<T>(d.M, 1, k0, ge, st, a));
+    if (k1 >= 0) FWI_HIP(launch_x_lossy<T>(d.M, 1, k1, ge, st, a));
     return FWI_OK;
   }
   int lossy_grad(int B, const T* c, const X2Args<T>& a, bool adj_only, hipStream_t st) {

@@ -37,7 +37,9 @@ namespace fwi {
 // FWI_AXIS_MAX_NT      largest axis-pass workgroup (one thread per 8 elements)
 // FWI_PITCH_BYTES      the spectrum row pitch px is a multiple of this
 // FWI_XVEL_LDS_BUDGET  x-lines per X1 workgroup = budget / (M sizeof(T)), odd
-// FWI_XDEN_LDS_BUDGET  the same for X2
+// FWI_XDEN_LDS_BUDGET  the same for X2 (and the lossy density pass)
+// FWI_XEOS_LDS_BUDGET  the same for the lossy equation-of-state pass (3, 5, 7
+//                      lines at M = 224 FP32: 192, 221, 210 us per launch)
 // Measured on the 448x448x224 FP32 step (per-pass HIP-event times): 128-byte
 // tiles on a 128-byte pitch are fastest overall; a 64-byte pitch makes half
 // of the 128-byte tile rows straddle two cache lines, a 256-byte pitch slows
@@ -59,6 +61,9 @@ namespace fwi {
 #endif
 #ifndef FWI_XDEN_LDS_BUDGET
 #define FWI_XDEN_LDS_BUDGET 3072
+#endif
+#ifndef FWI_XEOS_LDS_BUDGET
+#define FWI_XEOS_LDS_BUDGET 3072
 #endif
 enum AxisKind { AK_Y = 0, AK_ZMINUS = 1, AK_ZPLUS = 2 };
 // axis-pass tile width in complex elements for a row segment of TB bytes
@@ -89,6 +94,7 @@ template <typename T> constexpr int odd_lpb(int budget, int M) {
 }
 template <typename T> constexpr int x_lpb_vel(int M) { return odd_lpb<T>(FWI_XVEL_LDS_BUDGET, M); }
 template <typename T> constexpr int x_lpb_den(int M) { return odd_lpb<T>(FWI_XDEN_LDS_BUDGET, M); }
+template <typename T> constexpr int x_lpb_eos(int M) { return odd_lpb<T>(FWI_XEOS_LDS_BUDGET, M); }
 template <typename T> constexpr int x_lpb(int M) { return odd_lpb<T>(4096, M); }
 constexpr int X_NT = 256;
 
@@ -1216,7 +1222,7 @@ __global__ void __launch_bounds__(X_NT) k_x_lossy_rho(X2Args<T> a) {
 template <typename T, int M, int KIND>
 __global__ void __launch_bounds__(X_NT) k_x_lossy_eos(X2Args<T> a) {
   using C = cplx<T>;
-  constexpr int LPB = x_lpb_den<T>(M);
+  constexpr int LPB = x_lpb_eos<T>(M);
   constexpr int TWP = 2 * LPB;        // B[s] in columns 0.., A[d] in LPB..
   __shared__ C buf[(M + 1) * TWP];
   __shared__ C twl[XTw<M>::N];
