@@ -5,6 +5,7 @@
     python -m paper_2102_00755_amd.bench_forms lbfgs [--n 4954176] [--m 64]
     python -m paper_2102_00755_amd.bench_forms multigrid
     python -m paper_2102_00755_amd.bench_forms lossy [--steps 2] [--nt 2200]
+    python -m paper_2102_00755_amd.bench_forms latency [--steps 20]
 
 batched : 16 independent Rademacher-encoded TR gradients on 128^3 (phantom
           seeds 300..315, encoding seeds 1300..1315), run (a) one after
@@ -20,6 +21,9 @@ serve   : Poisson-arriving forward / gradient requests (50/50) over the grid
 lbfgs   : the SLBFGS two-loop recursion (64 pairs) and pair push at |Gamma| of
           the full workload, with their algorithmic bandwidth.
 multigrid: grid transfers between the 1 mm and 0.5 mm levels of the full box.
+latency : p50 / p99 of repeated plain encoded TR gradients (one at a time, each
+          synchronised): --steps solves of the full workload and 5x as many
+          of the 128^3 workload.
 lossy   : the encoded TR gradient of the full workload (448x448x224, 2200
           steps) with power-law absorption (0.75 dB MHz^-1.5 cm^-1, y = 1.5,
           TR with the sign of tau switched) against the same gradient without
@@ -283,9 +287,37 @@ def lossy(args) -> dict:
     return out
 
 
+def latency(args) -> dict:
+    from synth import make_config
+    out = {"form": "latency"}
+    for name, reps in (("c128", 5 * args.steps), ("full", args.steps)):
+        prob = make_config(name, nt=args.nt if name == "full" else None)
+        h = fwi.Handle.from_problem(prob, precision=4)
+        dev = h.device
+        c_eval, c_true, S, w = (t.to(dev) for t in _gradient_inputs(prob, dev, torch.float32))
+        obs = h.forward(c_true, S, w)
+        grad = torch.empty((1, *h.shape), device=dev, dtype=torch.float32)
+        h.gradient(c_eval, S, w, obs, out=grad)
+        torch.cuda.synchronize()
+        lat = []
+        for i in range(reps):
+            t0 = time.perf_counter()
+            h.gradient(c_eval, S, w, obs, out=grad)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t0)
+            if name == "full":
+                print(json.dumps({"solve": i, "s": lat[-1]}), flush=True)
+        ms = np.array(lat) * 1e3
+        out[name] = {"solves": reps, "p50_ms": float(np.percentile(ms, 50)), "p99_ms": float(np.percentile(ms, 99)),
+                     "min_ms": float(ms.min()), "max_ms": float(ms.max()),
+                     "Mcell_steps_per_s_p50": 3.0 * prob.n_cells * prob.nt / (np.percentile(ms, 50) / 1e3) / 1e6}
+        h.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("form", choices=["batched", "serve", "lbfgs", "multigrid", "lossy"])
+    ap.add_argument("form", choices=["batched", "serve", "lbfgs", "multigrid", "lossy", "latency"])
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--nt", type=int, default=None)
@@ -296,7 +328,7 @@ def main():
     ap.add_argument("--m", type=int, default=64)
     args = ap.parse_args()
     res = {"batched": batched, "serve": serve, "lbfgs": lbfgs, "multigrid": multigrid,
-           "lossy": lossy}[args.form](args)
+           "lossy": lossy, "latency": latency}[args.form](args)
     print(json.dumps(res), flush=True)
 
 
