@@ -666,8 +666,8 @@ template <typename T> struct Engine : EngineBase {
     a.tr_state_mode = 1; a.tape_row = N - 1; a.ring_c = 0; a.step = 0;
     if ((rc = lossy_eos(B, SP_DIRICHLET, -1, a, st))) return rc;
     a.tr_state_mode = 0;
-    if (N == 1) {  // p_tr^(1) = 0
-      if ((rc = fill<T>(ring, (long long)B * 3 * d.n_gam, (T)0, st))) return rc;
+    if (N == 1) {  // p_tr^(1) = 0 (ring slot 1; slot 0 holds p_tr^(0))
+      if ((rc = zero_ring_slot(B, 1, st))) return rc;
     }
     if (N >= 2) {  // advance the TR by one step to get ahead of the adjoint
       if ((rc = step_spectral(tr0, B, tr0, B, st))) return rc;
@@ -873,8 +873,8 @@ template <typename T> struct Engine : EngineBase {
     a.tape_row = N - 1; a.ring_c = 0; a.step = 0;
     if ((rc = launch_x2(XM_TRONLY, B, a, st))) return rc;
     a.tr_state_mode = 0;
-    if (N == 1) {  // p_tr^(1) = 0
-      if ((rc = fill<T>(ring, (long long)B * 3 * d.n_gam, (T)0, st))) return rc;
+    if (N == 1) {  // p_tr^(1) = 0 (ring slot 1; slot 0 holds p_tr^(0))
+      if ((rc = zero_ring_slot(B, 1, st))) return rc;
     }
     if (N >= 2) {  // advance the TR by one step to get ahead of the adjoint
       if ((rc = step_spectral(tr0, B, tr0, B, st))) return rc;
@@ -911,6 +911,12 @@ template <typename T> struct Engine : EngineBase {
     }
     timer.active = false;
     return scatter_grad(B, grad, st);
+  }
+  int zero_ring_slot(int B, int slot, hipStream_t st) {
+    int rc;
+    for (int b = 0; b < B; ++b)
+      if ((rc = fill<T>(ring + ((size_t)b * 3 + slot) * d.n_gam, (long long)d.n_gam, (T)0, st))) return rc;
+    return FWI_OK;
   }
   // G on Gamma -> full grid, zero elsewhere
   int scatter_grad(int B, T* grad, hipStream_t st) {

@@ -163,3 +163,27 @@ def test_absorption_argument_errors():
     with pytest.raises(FwiError):
         h.gradient(torch.from_numpy(prob.c_eval), torch.from_numpy(S), torch.from_numpy(w), torch.from_numpy(obs))
     h.close()
+
+
+@pytest.mark.parametrize("nt", [1, 2, 3])
+def test_lossy_few_time_steps_match_oracle(nt):
+    print(f"lossy few steps nt={nt}", flush=True)
+    prob = make_small(shape=SHAPES[1], nt=nt, n_src=2, n_rec=12, layer=1, precision=8)
+    w, _ = _inputs(prob)
+    S = random_traces(prob.nt, prob.n_src, seed=15)   # nonzero from the first step
+    sch = ks.scheme_for(prob)
+    a0 = lo.db_to_neper(A_DB, 1.5)
+    los = lo.Lossy(sch, a0, 1.5)
+    r = random_traces(prob.nt, prob.n_rec, seed=14, scale=1e-3)
+    D, G, _ = lo.tr_gradient(los, prob.c_eval, prob.src_ijk, S, w, prob.rec_ijk, None, prob.gamma, prob.boundary,
+                             prob.nt, residual=r)
+    h = handle(prob, 8)
+    h.set_absorption(a0, 1.5)
+    c = torch.from_numpy(prob.c_eval)
+    h.forward(c, torch.from_numpy(S), torch.from_numpy(w), save_tape=True)
+    mis, grad = h.backward(c, torch.from_numpy(r))
+    gmask = prob.gamma.astype(bool)
+    assert abs(float(mis[0]) - D) <= 1e-12 * D
+    assert np.linalg.norm(G[gmask]) > 0
+    assert rel(grad[0].cpu().numpy()[gmask], G[gmask]) < 1e-9
+    h.close()

@@ -157,3 +157,30 @@ def test_tr_gradient_from_final_state_matches_oracle(precision, tol):
     assert abs(float(mis[0]) - D) <= 1e-6 * D
     assert rel(grad[0].cpu().numpy()[g], G[g]) < tol
     h.close()
+
+
+@pytest.mark.parametrize("nt", [1, 2, 3])
+def test_few_time_steps_match_oracle(nt):
+    # degenerate horizons of Alg. 1: N = 1 has no TR pre-step and only the
+    # adjoint-only iterations, N = 2 no paired iteration, N = 3 one
+    print(f"few steps nt={nt}", flush=True)
+    prob = make_small(shape=SHAPES[1], nt=nt, n_src=2, n_rec=12, layer=1, precision=8)
+    w, _ = _inputs(prob)
+    S = random_traces(prob.nt, prob.n_src, seed=15)   # nonzero from the first step
+    sch = ks.scheme_for(prob)
+    r = random_traces(prob.nt, prob.n_rec, seed=13, scale=1e-3)
+    D, G, _ = ks.tr_gradient(sch, prob.c_eval, prob.src_ijk, S, w, prob.rec_ijk, None, prob.gamma,
+                             prob.boundary, prob.nt, residual=r)
+    h = handle(prob, 8)
+    c = torch.from_numpy(prob.c_eval)
+    h.forward(c, torch.from_numpy(S), torch.from_numpy(w), save_tape=True)
+    mis, grad = h.backward(c, torch.from_numpy(r))
+    gmask = prob.gamma.astype(bool)
+    assert abs(float(mis[0]) - D) <= 1e-12 * D
+    got = grad[0].cpu().numpy()
+    if nt == 1:   # p_adj^(0) is the injection alone: zero on Gamma, so G = 0
+        assert np.all(G == 0) and np.all(got == 0)
+    else:
+        assert np.linalg.norm(G[gmask]) > 0
+        assert rel(got[gmask], G[gmask]) < 1e-9
+    h.close()
