@@ -3,7 +3,8 @@
 The oracle needs minutes at these sizes, so tests/golden/make_golden.py (which
 calls only oracle/ and synth/) stored its outputs, rounded to FP32.  The GPU
 runs the same seeded inputs through the C-ABI in FP32 and in the launch
-configuration bench.py times (batch 1, full grid, PML 20 for 'fullgrid').
+configuration bench.py times (batch 1, full grid, PML 20 for 'fullgrid' and
+'lossyfull', the latter with power-law absorption).
 Tolerances: traces rel l2 <= 1e-4, misfit and gradients rel <= 1e-3.
 """
 
@@ -29,7 +30,7 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-@pytest.mark.parametrize("case", ["c128", "fullgrid"])
+@pytest.mark.parametrize("case", ["c128", "fullgrid", "lossyfull"])
 def test_large_case_matches_stored_oracle(case):
     import make_golden
     from paper_2102_00755_amd.fwi import Handle
@@ -41,6 +42,10 @@ def test_large_case_matches_stored_oracle(case):
     w = oracle.rademacher(prob.enc_seed, prob.n_src)
     assert np.array_equal(w, ref["w"])
     h = Handle.from_problem(prob, precision=4)
+    if case == "lossyfull":
+        from oracle import lossy
+        y = float(ref["y"])
+        h.set_absorption(lossy.db_to_neper(float(ref["alpha_db"]), y), y)
     S = torch.from_numpy(prob.src_signals())
     wt = torch.from_numpy(w)
     traces = h.forward(torch.from_numpy(prob.c_true), S, wt)[0].cpu().numpy()
