@@ -202,9 +202,9 @@ int fwi_set_tuning(fwi_handle* h, const fwi_tuning* t);
  *                 switches absorption off); read by every later call, so it
  *                 must stay allocated while absorption is set (the caller owns it)
  * The lossy step replaces the fused X2 pass by five launches (density
- * update, forward y, absorption z pass, inverse y, equation of state) and
- * runs without step graphs (FWI_GRAPH has no effect); FWI_TR_FINAL_STATE is
- * rejected with FWI_ERR_INVALID_ARG.  The first call that switches absorption
+ * update, forward y, absorption z pass, inverse y, equation of state);
+ * FWI_GRAPH replays it as a step graph like the lossless step;
+ * FWI_TR_FINAL_STATE is rejected with FWI_ERR_INVALID_ARG.  The first call that switches absorption
  * on allocates batch x |Gamma| values of device memory (FWI_ERR_OOM on
  * failure).  Any call invalidates the saved tape.  Errors:
  * FWI_ERR_INVALID_ARG (nothing changed) for a NULL handle, alpha0 < 0 or not

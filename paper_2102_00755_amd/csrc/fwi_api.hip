@@ -648,7 +648,8 @@ template <typename T> struct Engine : EngineBase {
     if (d.n_gam == 0) return FWI_OK;
     const int blocks = (int)std::min<long long>((d.n_gam + 255) / 256, 4096);
     hipLaunchKernelGGL((k_lossy_grad<T>), dim3(blocks, B), dim3(256), 0, st, c, gam_lin, padj, ring, gacc,
-                       (int)d.n_gam, (long long)d.nfield, a.ring_a, a.ring_b, a.ring_c, adj_only ? 1 : 0);
+                       (int)d.n_gam, (long long)d.nfield, a.ring_a, a.ring_b, a.ring_c, adj_only ? 1 : 0,
+                       a.step_dev);
     FWI_HIP(hipGetLastError());
     return FWI_OK;
   }
@@ -674,7 +675,22 @@ template <typename T> struct Engine : EngineBase {
       a.tape_row = N - 2; a.ring_c = 1;
       if ((rc = lossy_eos(B, SP_DIRICHLET, -1, a, st))) return rc;
     }
-    for (int j = 0; j < N; ++j) {
+    int j0 = 0;
+    if (use_graph && N >= 3) {   // iterations j = 0 .. N-3 pair with TR steps 2 .. N-1
+      if ((rc = fill<int>(step_counter, 1, 0, st))) return rc;
+      X2Args<T> ag = a;
+      ag.step_dev = step_counter;
+      if ((rc = replay_graph([&]() -> int {
+             int r;
+             if ((r = step_spectral(0, B, tr0, 2 * B, st))) return r;
+             if ((r = lossy_eos(B, SP_ADJOINT, SP_DIRICHLET, ag, st))) return r;
+             if ((r = lossy_grad(B, c, ag, false, st))) return r;
+             return count_step(st);
+           }, N - 2, st)))
+        return rc;
+      j0 = N - 2;
+    }
+    for (int j = j0; j < N; ++j) {
       const int k = j + 2;
       a.step = j;
       a.ring_a = j % 3; a.ring_b = (j + 1) % 3; a.ring_c = k % 3;
@@ -805,8 +821,18 @@ template <typename T> struct Engine : EngineBase {
     if ((rc = zero_slots(tr0, B, st))) return rc;   // p^0 = 0, v = 0, rho = 0
     X2Args<T> a = x2_args(B, c);
     a.src_sig = src; a.w = w; a.traces = traces; a.tape = save ? tape : nullptr;
-    if (lossy) {   // eager launches (no step graph)
+    if (lossy) {
       lossy_args(a);
+      if (use_graph) {
+        if ((rc = fill<int>(step_counter, 1, 0, st))) return rc;
+        a.step_dev = step_counter;
+        return replay_graph([&]() -> int {
+          int r;
+          if ((r = step_spectral(tr0, B, tr0, B, st))) return r;
+          if ((r = lossy_eos(B, SP_SOURCE, -1, a, st))) return r;
+          return count_step(st);
+        }, p.nt, st);
+      }
       for (int n = 0; n < p.nt; ++n) {
         if ((rc = step_spectral(tr0, B, tr0, B, st))) return rc;
         a.step = n;

@@ -1200,7 +1200,9 @@ __global__ void __launch_bounds__(X_NT) k_x_lossy_rho(X2Args<T> a) {
   const int nl = min(LPB, a.d.nlines - l0);
   const int b = blockIdx.y;
   const Slot<T> sl = a.slots[KIND == SP_ADJOINT ? b : a.tr_off + b];
-  const StepIdx si{a.step, a.tape_row, a.ring_a, a.ring_b, a.ring_c};
+  // forward steps count n, adjoint / TR steps the paired iteration j (a
+  // replayed step graph reads either from a.step_dev)
+  const StepIdx si = KIND == SP_SOURCE ? step_indices<T, XM_FWD>(a) : step_indices<T, XM_PAIR>(a);
   const int state_mode = KIND == SP_DIRICHLET ? a.tr_state_mode : 0;
   density_update<T, M, LPB, TWP, TWPP, KIND, true, true>(a, si, sl, b, l0, nl, state_mode, 0, buf, bufp, spv,
                                                          spm, twl);
@@ -1234,6 +1236,7 @@ __global__ void __launch_bounds__(X_NT) k_x_lossy_eos(X2Args<T> a) {
   const Slot<T> sl = a.slots[KIND == SP_ADJOINT ? b : a.tr_off + b];
   const T* cb = a.c + (size_t)b * a.d.nfield;
   const T sgn = KIND == SP_DIRICHLET ? a.tr_tau_sign : (T)1;
+  const StepIdx si = KIND == SP_SOURCE ? step_indices<T, XM_FWD>(a) : step_indices<T, XM_PAIR>(a);
   using Ly = Lanes<LPB, M>;
   C ss[Ly::NI], cc[Ly::NI], aa[Ly::NI];
   lanes2d_all<LPB, M>([&](int i, int l, int n, bool) {
@@ -1271,11 +1274,11 @@ __global__ void __launch_bounds__(X_NT) k_x_lossy_eos(X2Args<T> a) {
     const int i0 = a.g.rec_off[l0], i1 = a.g.rec_off[l0 + nl];
     for (int i = i0 + (int)threadIdx.x; i < i1; i += X_NT) {
       const int l = local_line(a.g.rec_off, l0, nl, i);
-      a.traces[((size_t)b * a.d.nt + a.step) * a.d.n_rec + a.g.rec_id[i]] = p_at<T, TWP>(buf, 0, l, a.g.rec_x[i]);
+      a.traces[((size_t)b * a.d.nt + si.step) * a.d.n_rec + a.g.rec_id[i]] = p_at<T, TWP>(buf, 0, l, a.g.rec_x[i]);
     }
     if (a.tape) {
       const int j0 = a.g.bnd_off[l0], j1 = a.g.bnd_off[l0 + nl];
-      T* trow = a.tape + ((size_t)b * a.d.nt + a.step) * a.d.n_bnd;
+      T* trow = a.tape + ((size_t)b * a.d.nt + si.step) * a.d.n_bnd;
       for (int i = j0 + (int)threadIdx.x; i < j1; i += X_NT) {
         const int l = local_line(a.g.bnd_off, l0, nl, i);
         trow[i] = p_at<T, TWP>(buf, 0, l, a.g.bnd_x[i]);
@@ -1283,7 +1286,7 @@ __global__ void __launch_bounds__(X_NT) k_x_lossy_eos(X2Args<T> a) {
     }
   } else {
     T* dst = KIND == SP_ADJOINT ? a.padj + (size_t)b * a.d.n_gam
-                                : a.ring + ((size_t)b * 3 + a.ring_c) * a.d.n_gam;
+                                : a.ring + ((size_t)b * 3 + si.rc) * a.d.n_gam;
     const int i0 = a.g.gam_off[l0], i1 = a.g.gam_off[l0 + nl];
     for (int i = i0 + (int)threadIdx.x; i < i1; i += X_NT) {
       const int l = local_line(a.g.gam_off, l0, nl, i);
@@ -1300,11 +1303,18 @@ __global__ void __launch_bounds__(X_NT) k_x_lossy_eos(X2Args<T> a) {
 
 // Gradient step of the lossy TR gradient (Alg. 1 form):
 //   G += 2 / c0^3 p_adj (p_tr^(j) - 2 p_tr^(j+1) + p_tr^(j+2))
-// with p_tr^(j+2) = 0 (and that ring slot cleared) when adj_only.
+// with p_tr^(j+2) = 0 (and that ring slot cleared) when adj_only; with
+// step_dev non-null the ring slots follow from the device iteration counter j.
 // grid: x over Gamma voxels, y over problems.
 template <typename T>
 __global__ void k_lossy_grad(const T* c, const int32_t* gam_lin, const T* padj, T* ring, double* gacc, int n_gam,
-                             long long nfield, int ra, int rb, int rc, int adj_only) {
+                             long long nfield, int ra, int rb, int rc, int adj_only, const int* step_dev) {
+  if (step_dev) {
+    const int j = *step_dev;
+    ra = j % 3;
+    rb = (j + 1) % 3;
+    rc = (j + 2) % 3;
+  }
   const int b = blockIdx.y;
   T* rg = ring + (size_t)b * 3 * n_gam;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_gam; i += gridDim.x * blockDim.x) {

@@ -187,3 +187,59 @@ def test_lossy_few_time_steps_match_oracle(nt):
     assert np.linalg.norm(G[gmask]) > 0
     assert rel(grad[0].cpu().numpy()[gmask], G[gmask]) < 1e-9
     h.close()
+
+
+def test_lossy_autograd_backward_is_the_lossy_tr_gradient():
+    # the differentiable forward (autograd) on a handle with absorption: the
+    # backward of 1/2 ||f - f_obs||^2 is the lossy TR gradient of the oracle
+    from paper_2102_00755_amd.autograd import simulate
+    prob = make_small(shape=SHAPES[0], nt=40, n_src=2, n_rec=12, layer=2, precision=8)
+    w, S = _inputs(prob)
+    sch = ks.scheme_for(prob)
+    a0 = lo.db_to_neper(A_DB, 1.5)
+    los = lo.Lossy(sch, a0, 1.5)
+    obs = lo.forward(los, prob.c_true, prob.src_ijk, S, w, prob.rec_ijk, prob.nt)["traces"]
+    D, G, _ = lo.tr_gradient(los, prob.c_eval, prob.src_ijk, S, w, prob.rec_ijk, obs, prob.gamma, prob.boundary,
+                             prob.nt)
+    h = handle(prob, 8)
+    h.set_absorption(a0, 1.5)
+    c = torch.from_numpy(prob.c_eval).to(h.device).requires_grad_(True)
+    f = simulate(h, c, torch.from_numpy(S).to(h.device), torch.from_numpy(w).to(h.device))
+    loss = 0.5 * ((f - torch.from_numpy(obs).to(h.device)) ** 2).sum()
+    loss.backward()
+    gmask = prob.gamma.astype(bool)
+    assert abs(float(loss.detach()) - D) <= 1e-10 * D
+    assert rel(c.grad.cpu().numpy()[gmask], G[gmask]) < 1e-9
+    h.close()
+
+
+def test_lossy_graph_replay_equals_eager():
+    # FWI_GRAPH: the lossy step captured once per call and replayed; every
+    # replayed call, with eager work in between, equals the eager result bit
+    # for bit (batch of two problems)
+    prob = make_small(shape=SHAPES[1], nt=40, n_src=2, n_rec=12, layer=2, precision=4)
+    h = handle(prob, 4, batch=2)
+    h.set_absorption(lo.db_to_neper(A_DB, 1.5), 1.5)
+    S = torch.from_numpy(np.stack([prob.src_signals()] * 2))
+    w = torch.from_numpy(np.stack([oracle.rademacher(7, 2), oracle.rademacher(8, 2)]))
+    c = torch.from_numpy(np.stack([prob.c_eval, prob.c_true]))
+    obs = torch.from_numpy(np.stack([random_traces(prob.nt, prob.n_rec, 3, 1e-3),
+                                     random_traces(prob.nt, prob.n_rec, 4, 1e-3)]))
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        h.use_graph = False
+        tr_e = h.forward(c, S, w).clone()
+        m_e, g_e = h.gradient(c, S, w, obs)
+        m_e, g_e = m_e.clone(), g_e.clone()
+        for rep in range(3):
+            h.use_graph = True
+            tr_g = h.forward(c, S, w)
+            m_g, g_g = h.gradient(c, S, w, obs)
+            side.synchronize()
+            assert torch.equal(tr_g, tr_e), rep
+            assert torch.equal(g_g, g_e), rep
+            assert torch.equal(m_g, m_e), rep
+            h.use_graph = False            # eager work between the replays
+            h.forward(c, S, w)
+            side.synchronize()
+    h.close()
