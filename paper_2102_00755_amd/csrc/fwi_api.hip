@@ -710,8 +710,8 @@ template <typename T> struct Engine : EngineBase {
 
   int set_absorption(double alpha0, double y, const void* field, int flip) override {
     if (!std::isfinite(alpha0) || alpha0 < 0.0) return fail(FWI_ERR_INVALID_ARG, "alpha0 must be finite and >= 0");
-    tape_valid = false;
     if (alpha0 == 0.0 && !field) {
+      tape_valid = false;
       lossy = false;
       a0f = nullptr;
       a0u = 0.0;
@@ -728,6 +728,7 @@ template <typename T> struct Engine : EngineBase {
       }
       padj = (T*)mem_padj.p;
     }
+    tape_valid = false;
     lossy = true;
     a0u = alpha0;
     a0f = (const T*)field;

@@ -1219,7 +1219,8 @@ __global__ void __launch_bounds__(X_NT) k_x_lossy_rho(X2Args<T> a) {
 //   tau = -2 alpha0 c0^{y-1},  eta = 2 alpha0 c0^y tan(pi y / 2),
 // sgn = a.tr_tau_sign for the TR (KIND SP_DIRICHLET), else +1; then the
 // outputs of KIND (forward: traces f^n and tape g^n; adjoint: p on Gamma to
-// a.padj; TR: p on Gamma to ring slot a.ring_c) and the forward x transform
+// a.padj; TR: p on Gamma to ring slot a.ring_c, or (j + 2) mod 3 in a replayed
+// step graph) and the forward x transform
 // of p into field 0.
 template <typename T, int M, int KIND>
 __global__ void __launch_bounds__(X_NT) k_x_lossy_eos(X2Args<T> a) {

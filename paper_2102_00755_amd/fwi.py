@@ -256,15 +256,16 @@ class Handle:
         number or a per-voxel field [nz, ny, nx] (kept on the device by the handle
         for as long as absorption is set); alpha0 = 0 with no field switches it
         off.  tr_flip: the TR simulation switches the sign of tau (Sec. 3.1)."""
-        ptr = None
-        self._alpha0_field = None
+        ptr, f = None, None
         if field is not None:
             f = self._t(field, self.shape)[0].contiguous()
-            self._alpha0_field = f
             ptr = ctypes.c_void_p(f.data_ptr())
         torch.cuda.synchronize(self.device)
         _check(self._lib.fwi_set_absorption(self._h, float(alpha0), float(y), ptr, 1 if tr_flip else 0),
                "fwi_set_absorption")
+        # the library now reads this field (or none): keep it alive; on an
+        # error above the previous field stays in use and stays referenced
+        self._alpha0_field = f
         self.tape_token += 1
 
     def timing_enable(self, every: int) -> None:

@@ -156,9 +156,18 @@ def test_absorption_argument_errors():
     for a0, y in ((1e-3, 1.0), (1e-3, 2.0), (1e-3, 0.0), (-1.0, 1.5), (float("nan"), 1.5)):
         with pytest.raises(FwiError):
             h.set_absorption(a0, y)
-    h.set_absorption(lo.db_to_neper(A_DB, 1.5), 1.5)
-    h.tr_final_state = True
     w, S = _inputs(prob)
+    c, Sg, wg = torch.from_numpy(prob.c_true), torch.from_numpy(S), torch.from_numpy(w)
+    # a rejected call leaves the previous absorption (and its field) in use
+    a0 = lo.db_to_neper(A_DB, 1.5)
+    h.set_absorption(0.0, 1.5, field=torch.full(prob.shape, a0, dtype=torch.float64))
+    before = h.forward(c, Sg, wg).clone()
+    with pytest.raises(FwiError):
+        h.set_absorption(0.0, 1.0, field=torch.full(prob.shape, 3 * a0, dtype=torch.float64))
+    torch.cuda.empty_cache()
+    assert torch.equal(h.forward(c, Sg, wg), before)
+    h.set_absorption(a0, 1.5)
+    h.tr_final_state = True
     obs = random_traces(prob.nt, prob.n_rec, seed=3, scale=1e-3)
     with pytest.raises(FwiError):
         h.gradient(torch.from_numpy(prob.c_eval), torch.from_numpy(S), torch.from_numpy(w), torch.from_numpy(obs))
