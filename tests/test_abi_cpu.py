@@ -91,6 +91,16 @@ def test_set_tuning_rejects_null_handle_and_bad_values():
     assert lib.fwi_get_tuning(None, ctypes.byref(t)) == L.FWI_ERR_INVALID_ARG
 
 
+def test_set_absorption_rejects_null_handle_and_db_conversion_matches_oracle():
+    L, lib = _lib()
+    assert lib.fwi_set_absorption(None, 1e-3, 1.5, None, 1) == L.FWI_ERR_INVALID_ARG
+    from oracle import lossy
+    from paper_2102_00755_amd.fwi import db_to_neper
+    for a_db, y in ((0.75, 1.5), (15.0, 0.6), (0.5, 1.1)):
+        want = lossy.db_to_neper(a_db, y)
+        assert abs(db_to_neper(a_db, y) - want) <= 1e-15 * want
+
+
 def test_autotune_choice_and_cache(tmp_path):
     from paper_2102_00755_amd import autotune
     per = {64: {"y_fwd": 1.0, "y_inv": 1.0, "y_vel_q": 1.0, "z_minus": 2.0, "z_plus": 1.0},
