@@ -40,18 +40,20 @@ namespace fwi {
 // FWI_XDEN_LDS_BUDGET  the same for X2 (and the lossy density pass)
 // FWI_XEOS_LDS_BUDGET  the same for the lossy equation-of-state pass (3, 5, 7
 //                      lines at M = 224 FP32: 192, 221, 210 us per launch)
-// Measured on the 448x448x224 FP32 step (per-pass HIP-event times): 128-byte
-// tiles on a 128-byte pitch are fastest overall; a 64-byte pitch makes half
-// of the 128-byte tile rows straddle two cache lines, a 256-byte pitch slows
-// the y and z passes (row stride 2 KiB).
+// Measured on the 448x448x224 FP32 gradient (same box, alternating runs):
+// 128-byte y tiles with 64-byte z tiles (XCD-paired, see tile_linear) give
+// 25 140 Mcell-steps/s against 24 995 with 128-byte z tiles and 24 600 with
+// 64-byte y tiles; the pitch stays 128 bytes (a 64-byte pitch makes half of
+// the 128-byte rows straddle two cache lines, a 256-byte pitch slows the y and
+// z passes), and 256-byte z tiles are slower (fewer workgroups per CU).
 #ifndef FWI_Y_TILE_BYTES
 #define FWI_Y_TILE_BYTES 128
 #endif
 #ifndef FWI_ZM_TILE_BYTES
-#define FWI_ZM_TILE_BYTES 128
+#define FWI_ZM_TILE_BYTES 64
 #endif
 #ifndef FWI_ZP_TILE_BYTES
-#define FWI_ZP_TILE_BYTES 128
+#define FWI_ZP_TILE_BYTES 64
 #endif
 #ifndef FWI_AXIS_MAX_NT
 #define FWI_AXIS_MAX_NT 512
@@ -209,6 +211,21 @@ __device__ __forceinline__ void tile_load(cplx<T>* buf, const cplx<T>* g, size_t
   tw_commit<T, L, NT>(twl, tt);
 }
 
+// Linear tile index of an axis-pass workgroup.  With 64-byte row segments two
+// neighbouring tiles share every 128-byte line.  Workgroups are dispatched
+// round-robin over the eight XCDs, each with its own L2, so within every group
+// of 16 workgroups the mapping gives both halves of a line to workgroups b and
+// b + 8, which run on the same XCD at the same time: their half-line writes
+// merge in that L2 instead of reaching HBM as read-modify-writes.  Measured at
+// 448x448x224 FP32 with 64-byte z tiles: Z2 2.9 -> 3.6 TB/s.  128-byte tiles
+// keep the identity.
+template <int TBYTES> __device__ __forceinline__ int tile_linear() {
+  const int b = blockIdx.x;
+  if (TBYTES >= 128) return b;
+  const int g16 = gridDim.x & ~15;
+  return b < g16 ? (b & ~15) + 2 * (b & 7) + ((b >> 3) & 1) : b;
+}
+
 // Y pass: in-place FFT along y of nf fields per slot.  L == ny.
 template <typename T, int L, bool INV, int TB>
 __global__ void __launch_bounds__(axis_nt(L, tile_tw<T, TB>()))
@@ -219,8 +236,9 @@ k_axis_y(AxisArgs<T> a) {
   __shared__ C buf[L * TW];
   __shared__ C twl[L];
   const int ntx = (a.d.px + TW - 1) / TW;   // tiles per spectrum row
-  const int tile = blockIdx.x % ntx;
-  const int z = blockIdx.x / ntx;
+  const int tl = tile_linear<TB>();
+  const int tile = tl % ntx;
+  const int z = tl / ntx;
   const int s = slot_of(blockIdx.y / a.nf, a.slot0, a.na, a.slot1);
   const int f = a.f0 + blockIdx.y % a.nf;
   const size_t px = a.d.px;
@@ -243,8 +261,9 @@ k_axis_z(AxisArgs<T> a) {
   __shared__ C buf[L * TW];
   __shared__ C twl[L];
   const int ntx = (a.d.px + TW - 1) / TW;   // tiles per spectrum row
-  const int tile = blockIdx.x % ntx;
-  const int y = blockIdx.x / ntx;
+  const int tl = tile_linear<TB>();
+  const int tile = tl % ntx;
+  const int y = tl / ntx;
   const int s = slot_of(blockIdx.y / a.nf, a.slot0, a.na, a.slot1);
   const int f = a.f0 + blockIdx.y % a.nf;
   const size_t px = a.d.px;
@@ -313,8 +332,9 @@ k_axis_z_minus(AxisArgs<T> a) {
   __shared__ C buf[L * TW];
   __shared__ C twl[L];
   const int ntx = (a.d.px + TW - 1) / TW;   // tiles per spectrum row
-  const int tile = blockIdx.x % ntx;
-  const int y = blockIdx.x / ntx;
+  const int tl = tile_linear<TB>();
+  const int tile = tl % ntx;
+  const int y = tl / ntx;
   const int s = slot_of(blockIdx.y / a.nf, a.slot0, a.na, a.slot1);
   const int f = a.f0 + blockIdx.y % a.nf;
   const size_t px = a.d.px;
@@ -352,8 +372,9 @@ k_axis_z_plus(AxisArgs<T> a) {
   __shared__ C buf[L * TW];
   __shared__ C twl[L];
   const int ntx = (a.d.px + TW - 1) / TW;   // tiles per spectrum row
-  const int tile = blockIdx.x % ntx;
-  const int y = blockIdx.x / ntx;
+  const int tl = tile_linear<TB>();
+  const int tile = tl % ntx;
+  const int y = tl / ntx;
   const int s = slot_of(blockIdx.y, a.slot0, a.na, a.slot1);
   const size_t px = a.d.px;
   const size_t rstride = (size_t)a.d.ny * px;
@@ -416,8 +437,9 @@ k_axis_z_frac(AxisArgs<T> a) {
   __shared__ C buf[L * TW];
   __shared__ C twl[L];
   const int ntx = (a.d.px + TW - 1) / TW;   // tiles per spectrum row
-  const int tile = blockIdx.x % ntx;
-  const int y = blockIdx.x / ntx;
+  const int tl = tile_linear<TB>();
+  const int tile = tl % ntx;
+  const int y = tl / ntx;
   const int s = slot_of(blockIdx.y / a.nf, a.slot0, a.na, a.slot1);
   const int f = a.f0 + blockIdx.y % a.nf;
   const size_t px = a.d.px;
@@ -469,8 +491,9 @@ k_axis_y_split(AxisArgs<T> a) {
   __shared__ C twl[L];
   __shared__ C sfl[L];
   const int ntx = (a.d.px + TW - 1) / TW;   // tiles per spectrum row
-  const int tile = blockIdx.x % ntx;
-  const int z = blockIdx.x / ntx;
+  const int tl = tile_linear<TB>();
+  const int tile = tl % ntx;
+  const int z = tl / ntx;
   const int part = blockIdx.y & 1;
   const int s = slot_of(blockIdx.y >> 1, a.slot0, a.na, a.slot1);
   const size_t px = a.d.px;
@@ -554,8 +577,9 @@ k_axis_y_vel(AxisArgs<T> a) {
   __shared__ C sfl[L];   // part 0: i k_y e^{+i k_y dy/2}
   __shared__ T lml[L];   // part 0: Lambda^s_y
   const int ntx = (a.d.px + TW - 1) / TW;   // tiles per spectrum row
-  const int tile = blockIdx.x % ntx;
-  const int z = blockIdx.x / ntx;
+  const int tl = tile_linear<TB>();
+  const int tile = tl % ntx;
+  const int z = tl / ntx;
   const Slot<T>& sl = a.slots[slot_of(blockIdx.y, a.slot0, a.na, a.slot1)];
   const size_t px = a.d.px;
   const size_t off = (size_t)z * L * px + (size_t)tile * TW;
