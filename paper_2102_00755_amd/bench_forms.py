@@ -11,7 +11,8 @@ batched : 16 independent Rademacher-encoded TR gradients on 128^3 (phantom
           seeds 300..315, encoding seeds 1300..1315), run (a) one after
           another on a batch-1 handle and (b) in one batch-16 handle whose
           passes cover all problems per launch, with the time step captured in
-          a hipGraph; reports Mcell-steps/s and per-solve latency of both.
+          a hipGraph, each handle with the autotuner's tile widths; reports
+          Mcell-steps/s and per-solve latency of both.
 serve   : Poisson-arriving forward / gradient requests (50/50) over the grid
           levels 96^3 @ 1.0 mm (300 steps), 160^3 @ 0.75 mm (600) and
           224x224x112 @ 0.5 mm (1200), admitted by HBM footprint; the arrival
@@ -35,12 +36,14 @@ from __future__ import annotations
 
 import argparse
 import json
+import os
+import tempfile
 import time
 
 import numpy as np
 import torch
 
-from . import fwi
+from . import autotune, fwi
 from .serving import Level, Server
 
 
@@ -73,8 +76,10 @@ def batched(args) -> dict:
     S = S.unsqueeze(0).expand(B, -1, -1).contiguous()
     side = torch.cuda.Stream(device=dev)
     out = {}
+    cache = os.path.join(tempfile.mkdtemp(), "tuning.json")
     with torch.cuda.stream(side):
         hb = fwi.Handle(**kw, batch=B)
+        out["tuning_batched"] = autotune.apply(hb, cache=cache)   # tile widths measured for this grid
         hb.use_graph = True
         obs = hb.forward(c_true, S, W)
         side.synchronize()
@@ -85,6 +90,7 @@ def batched(args) -> dict:
         side.synchronize()
         t_b = time.perf_counter() - t0
         h1 = fwi.Handle(**kw, batch=1)
+        out["tuning_single"] = autotune.apply(h1, cache=cache)
         h1.use_graph = True
         h1.gradient(c_eval[0], S[0], W[0], obs[0])
         side.synchronize()
