@@ -16,7 +16,8 @@ batched : 16 independent Rademacher-encoded TR gradients on 128^3 (phantom
 serve   : Poisson-arriving forward / gradient requests (50/50) over the grid
           levels 96^3 @ 1.0 mm (300 steps), 160^3 @ 0.75 mm (600) and
           224x224x112 @ 0.5 mm (1200), admitted by HBM footprint; the arrival
-          rate is set to ~80 % of the measured single-stream capacity;
+          rate is set to ~80 % of the measured single-stream capacity; each
+          level uses the autotuner's tile widths;
           reports p50/p99 latency and Mcell-steps/s against the same requests
           solved one at a time.
 lbfgs   : the SLBFGS two-loop recursion (64 pairs) and pair push at |Gamma| of
@@ -139,9 +140,14 @@ def serve(args) -> dict:
         obs[n] = h.forward(torch.from_numpy(p.c_true), torch.from_numpy(p.src_signals()),
                            torch.from_numpy(fwi.rademacher(p.enc_seed, p.n_src)))[0].cpu()
         h.close()
+    # tile widths of each level from the autotuner (applied to the solo handles
+    # and to every handle the server creates)
+    cache = os.path.join(tempfile.mkdtemp(), "tuning.json")
     # single-stream capacity: every request alone, one after another
     solo_lat = []
     hs = {n: fwi.Handle.from_problem(p) for n, p in probs.items()}
+    for lv in levels:
+        lv.tuning = autotune.apply(hs[lv.name], cache=cache)
     for n in names:   # warm-up
         hs[n].forward(torch.from_numpy(probs[n].c_eval), torch.from_numpy(probs[n].src_signals()),
                       torch.from_numpy(fwi.rademacher(1, probs[n].n_src)))
@@ -173,7 +179,8 @@ def serve(args) -> dict:
     st = srv.stats()
     srv.close()
     return {
-        "form": "serve", "requests": len(reqs), "levels": names, "arrival_rate_per_s": rate,
+        "form": "serve", "tuning": {lv.name: lv.tuning for lv in levels}, "requests": len(reqs),
+        "levels": names, "arrival_rate_per_s": rate,
         "served_Mcell_steps_per_s": st["Mcell-steps/s"], "served_p50_ms": st["p50_ms"],
         "served_p99_ms": st["p99_ms"], "solo_Mcell_steps_per_s": work / t_solo / 1e6,
         "solo_p50_ms": float(np.percentile(np.array(solo_lat) * 1e3, 50)),

@@ -34,10 +34,13 @@ from . import fwi
 
 @dataclasses.dataclass
 class Level:
-    """One grid level: handle arguments (``fwi.problem_kwargs``) and precision."""
+    """One grid level: handle arguments (``fwi.problem_kwargs``) and precision;
+    ``tuning`` (optional, e.g. from ``autotune.apply``) is set on every handle
+    the server creates for the level."""
 
     name: str
     kwargs: dict
+    tuning: Optional[dict] = None
 
     @property
     def n_cells(self) -> int:
@@ -164,6 +167,8 @@ class Server:
             if self._used + fp > self.budget:
                 return None
         h = fwi.Handle(**self.levels[level].kwargs, batch=1, device=self.device.index or 0)
+        if self.levels[level].tuning:
+            h.tuning = self.levels[level].tuning
         self._used += fp
         self._all_handles.append(h)
         return h
