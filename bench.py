@@ -26,6 +26,9 @@ if ROOT not in sys.path:
 
 METRIC = "Mcell-steps/s of TR-gradient at 448x448x224 FP32; p50/p99 solve latency"
 PEAK_HBM_GBS = 8000.0
+# algorithmic HBM bytes per cell and simulation step of the nine-pass step
+# (43 field-sized reads and writes of 4 bytes; the pass table of the kernels)
+STEP_BYTES_PER_CELL = 172.0
 
 KERNEL_SYMBOLS = {
     "y_fwd": "k_axis_y<float, {ny}, false, {ty}>",
@@ -54,14 +57,20 @@ def measured_traffic(kernel: str, bytes_per_launch: float):
             h.update(fh.read())
     sha = h.hexdigest()
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_pmc.txt"))):
-        kv = {}
+        ratios, cur, file_sha = {}, None, None
         with open(path) as fh:
             for line in fh:
-                if ": " in line and not line.startswith(" "):
-                    k, v = line.rstrip("\n").split(": ", 1)
-                    kv[k] = v
-        if kv.get("kernel") == kernel and kv.get("source_sha256") == sha:
-            return round(float(kv["traffic_over_algorithmic"]) * bytes_per_launch, 1)
+                if ": " not in line or line.startswith(" "):
+                    continue
+                k, v = line.rstrip("\n").split(": ", 1)
+                if k == "kernel":
+                    cur = v
+                elif k == "traffic_over_algorithmic" and cur is not None:
+                    ratios[cur] = float(v)
+                elif k == "source_sha256":
+                    file_sha = v
+        if file_sha == sha and kernel in ratios:
+            return round(ratios[kernel] * bytes_per_launch, 1)
     return None
 
 
@@ -73,7 +82,9 @@ def parse():
     ap.add_argument("--config", default="full", help="synth config name (default: the full-size workload)")
     ap.add_argument("--nt", type=int, default=None, help="override the number of time steps")
     ap.add_argument("--timing-every", type=int, default=16, help="sample pass launches every k steps")
-    ap.add_argument("--cpu-nt", type=int, default=2, help="time steps of the oracle sample")
+    ap.add_argument("--cpu-nt", type=int, default=3, help="time steps of the oracle sample")
+    ap.add_argument("--cpu-nt-single", type=int, default=2,
+                    help="time steps of the single-thread oracle sample (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile-bytes", type=int, nargs=3, metavar=("Y", "ZM", "ZP"), default=None,
                     help="axis-pass tile bytes (fwi_set_tuning) instead of the library defaults")
@@ -81,10 +92,15 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(prob, nt_cpu: int) -> dict:
-    """FP64 oracle TR gradient of the same grid, geometry and medium on a
-    truncated horizon of nt_cpu steps, timed on this host."""
-    import numpy as np
+def executed_steps(nt: int) -> int:
+    """Wave-simulation steps one TR gradient of nt steps executes (Alg. 1):
+    nt forward, nt adjoint and nt - 1 TR steps (the TR pre-step and the
+    nt - 2 paired steps; TR step k >= nt is never run)."""
+    return 3 * nt - 1 if nt >= 2 else 2 * nt
+
+
+def _time_oracle(prob, nt_cpu: int, workers: int):
+    import numpy as np  # noqa: F401
 
     from oracle import kspace as ks
     from synth.configs import random_traces
@@ -92,23 +108,49 @@ def cpu_baseline(prob, nt_cpu: int) -> dict:
     w = ks.rademacher(prob.enc_seed, prob.n_src)
     S = prob.src_signals()[:nt_cpu]
     obs = random_traces(nt_cpu, prob.n_rec, seed=99, scale=1e-3)
-    t0 = time.perf_counter()
-    sch = ks.scheme_for(prob)
-    t1 = time.perf_counter()
-    ks.tr_gradient(sch, prob.c_eval, prob.src_ijk, S, w, prob.rec_ijk, obs, prob.gamma, prob.boundary, nt_cpu)
-    t2 = time.perf_counter()
-    work = 3.0 * prob.n_cells * nt_cpu
-    return {
-        "value": work / (t2 - t1) / 1e6,
+    saved = ks._WORKERS
+    ks._WORKERS = workers            # the FFT thread count the oracle's calls read
+    try:
+        t0 = time.perf_counter()
+        sch = ks.scheme_for(prob)
+        t1 = time.perf_counter()
+        ks.tr_gradient(sch, prob.c_eval, prob.src_ijk, S, w, prob.rec_ijk, obs, prob.gamma, prob.boundary,
+                       nt_cpu)
+        t2 = time.perf_counter()
+    finally:
+        ks._WORKERS = saved
+    return t1 - t0, t2 - t1
+
+
+def cpu_baseline(prob, nt_cpu: int, nt_single: int) -> dict:
+    """FP64 oracle TR gradient of the same grid, geometry and medium on a
+    truncated horizon, timed on this host: nt_cpu steps with the oracle's
+    FFT thread count, and nt_single steps with one thread.  The rate credits
+    only the simulation steps the truncated gradient executes."""
+    from oracle import kspace as ks
+
+    workers = int(ks._WORKERS)
+    setup, t = _time_oracle(prob, nt_cpu, workers)
+    steps = executed_steps(nt_cpu)
+    out = {
+        "value": prob.n_cells * steps / t / 1e6,
         "unit": "Mcell-steps/s",
-        "cores": int(ks._WORKERS),
+        "cores": workers,
         "kind": "oracle",
-        "sample": (f"FP64 oracle TR gradient (forward + adjoint + TR) on the same "
-                   f"{prob.shape[2]}x{prob.shape[1]}x{prob.shape[0]} grid, geometry and medium, "
-                   f"truncated to {nt_cpu} time steps; operator setup ({t1 - t0:.1f} s) excluded; "
-                   f"scipy.fft workers={ks._WORKERS}; host {os.cpu_count()} logical CPUs"),
-        "seconds": round(t2 - t1, 3),
+        "sample": (f"FP64 oracle TR gradient on the same {prob.shape[2]}x{prob.shape[1]}x{prob.shape[0]} "
+                   f"grid, geometry and medium, truncated to {nt_cpu} time steps = {steps} executed "
+                   f"simulation steps ({nt_cpu} forward, {nt_cpu} adjoint, {max(nt_cpu - 1, 0)} TR), "
+                   f"{t:.2f} s; rate = cells x executed steps / time; operator setup ({setup:.1f} s) "
+                   f"excluded; scipy.fft workers={workers}; host {os.cpu_count()} logical CPUs"),
+        "seconds": round(t, 3),
+        "executed_steps": steps,
     }
+    if nt_single > 0:
+        _, t1 = _time_oracle(prob, nt_single, 1)
+        s1 = executed_steps(nt_single)
+        out["single_worker"] = {"value": round(prob.n_cells * s1 / t1 / 1e6, 3), "cores": 1,
+                                "nt": nt_single, "executed_steps": s1, "seconds": round(t1, 3)}
+    return out
 
 
 def main():
@@ -220,6 +262,14 @@ def main():
             "gamma_voxels": int(prob.gamma.sum()), "boundary_voxels": int(prob.boundary.sum()),
         },
         "roofline": roof,
+        "whole_gradient": {
+            "bytes_per_cell_step": STEP_BYTES_PER_CELL,
+            "executed_steps": executed_steps(prob.nt),
+            "achieved_GBps": round(STEP_BYTES_PER_CELL * cells * executed_steps(prob.nt) * args.steps
+                                   / total / 1e9, 1),
+            "frac": round(STEP_BYTES_PER_CELL * cells * executed_steps(prob.nt) * args.steps
+                          / total / 1e9 / PEAK_HBM_GBS, 4),
+        },
         "per_pass": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                      for k, v in per_pass.items()},
         "misfit": misfit,
@@ -232,7 +282,7 @@ def main():
     del obs, grad, c_eval, c_true, S
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_nt)
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_nt, args.cpu_nt_single)
     print(json.dumps(out), flush=True)
 
 

@@ -60,9 +60,14 @@ enum {
   FWI_CHECK_FINITE = 4, /* check outputs are finite (reads a flag back)       */
   FWI_TR_FINAL_STATE = 8, /* start the TR run from the final forward state
                              instead of the paper's zero interior           */
-  FWI_GRAPH = 16          /* capture one time step in a hipGraph and replay it
+  FWI_GRAPH = 16,         /* capture one time step in a hipGraph and replay it
                              (step index read from device memory); results
                              are identical to eager launches                 */
+  FWI_MEAN = 32           /* fwi_gradient / fwi_backward: write the mean of the
+                             B gradients, (1/B) sum_b G_b summed in FP64 in the
+                             order b = 0..B-1, to ONE grid [nz][ny][nx]
+                             (averaging of independent encoded realisations,
+                             Sec. 3.2); misfit stays [B]                     */
 };
 
 /* Scheme parameters (App. B).  dt = cfl dx / c_max in the paper (Sec. 4.1). */
@@ -119,10 +124,25 @@ int fwi_rademacher(uint64_t seed, int32_t n, int8_t* w_out);
  * d_i tau later, d_i ~ U[0,1).  d_i is the i-th uniform of the same SplitMix64
  * stream as fwi_rademacher, taken at counter n + i (so weights and delays of
  * one seed are independent): d_i = (z >> 11) * 2^-53 with z its output, and
- * out[i] = floor(d_i * tau_steps + 1/2) whole time steps.  The caller shifts
- * each source signal (and each source's observed data) by out[i] steps and
- * runs nt + tau_steps steps.  Host arrays, n >= 0, tau_steps >= 0. */
+ * out[i] = floor(d_i * tau_steps + 1/2) whole time steps, to be passed to
+ * fwi_set_delays; the handle then runs nt = (signal length) + tau_steps steps
+ * and the caller's observed data are the delayed-encoded data.  Host arrays,
+ * n >= 0, tau_steps >= 0. */
 int fwi_delays(uint64_t seed, int32_t n, int32_t tau_steps, int32_t* out);
+
+/* Delayed source encoding (Sec. 3.2, eq. DelaySE): source i of problem b
+ * fires its signal delays[b][i] whole steps late, i.e. the injection of step n
+ * uses src_sig[b][n - delays[b][i]][i] (zero for n < delays[b][i]); the
+ * signals passed to fwi_forward / fwi_gradient stay unshifted.
+ *   delays  host [B][n_src] int32, each in [0, nt); copied into the handle
+ *           (rows b >= B are zero).  B = 0 (delays may be NULL) switches
+ *           delays off.
+ * Applies to every later fwi_forward and fwi_gradient of the handle (the
+ * adjoint and TR simulations inject no sources).  Synchronises the device
+ * first, so no call of the handle may be in flight on another thread.
+ * FWI_ERR_INVALID_ARG (nothing changed) for a NULL handle, B outside
+ * [0, batch], a NULL array with B > 0 or a delay outside [0, nt). */
+int fwi_set_delays(fwi_handle* h, int32_t B, const int32_t* delays);
 
 /* Forward simulation (Alg. 1 forward iteration) of B problems:
  *   c        [B][nz][ny][nx]  sound speed, in [c_min, c_max]
@@ -141,7 +161,8 @@ int fwi_forward(fwi_handle* h, int32_t B, const void* c, const void* src_sig,
  *   G = sum_j 2/c0^3 p_adj^(j) (p_tr^(j) - 2 p_tr^(j+1) + p_tr^(j+2))  on Gamma.
  *   obs      [B][nt][n_rec]   observed (encoded) data f^delta
  *   misfit   [B] double       output D
- *   grad     [B][nz][ny][nx]  output gradient, zero outside Gamma
+ *   grad     [B][nz][ny][nx]  output gradient, zero outside Gamma ([nz][ny][nx]:
+ *                             their mean, with FWI_MEAN)
  * Three wave simulations per problem (Sec. 3.1). */
 int fwi_gradient(fwi_handle* h, int32_t B, const void* c, const void* src_sig,
                  const int8_t* w, const void* obs, double* misfit, void* grad,

@@ -33,6 +33,7 @@ from .kspace import (  # noqa: F401
     State,
     rademacher,
     delays,
+    delayed_signals,
     splitmix64,
     forward,
     tr_gradient,

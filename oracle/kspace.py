@@ -86,6 +86,22 @@ def delays(seed: int, n: int, tau_steps: int) -> np.ndarray:
     return out
 
 
+def delayed_signals(src_sig, delay_steps, nt_total: int) -> np.ndarray:
+    """Delayed encoded sources (Sec. 3.2, eq. DelaySE): source i emits
+    s_i(t - d_i tau), i.e. its samples start delay_steps[i] steps late.
+    Returns [nt_total, n_src]: zero before each source's delay and after its
+    own samples run out."""
+    src = np.asarray(src_sig, dtype=np.float64)
+    nt, ns = src.shape
+    out = np.zeros((nt_total, ns))
+    for i in range(ns):
+        d = int(delay_steps[i])
+        for n in range(d, nt_total):
+            if n - d < nt:
+                out[n, i] = src[n - d, i]
+    return out
+
+
 # --------------------------------------------------------------------------
 # discretisation (App. B)
 # --------------------------------------------------------------------------

@@ -28,6 +28,7 @@ FWI_CHECK_INPUT = 2
 FWI_CHECK_FINITE = 4
 FWI_TR_FINAL_STATE = 8
 FWI_GRAPH = 16
+FWI_MEAN = 32
 
 SUPPORTED_LENGTHS = (8, 12, 16, 24, 32, 40, 48, 56, 64, 80, 96, 112, 128, 160, 224, 256, 448)
 
@@ -35,7 +36,7 @@ SUPPORTED_LENGTHS = (8, 12, 16, 24, 32, 40, 48, 56, 64, 80, 96, 112, 128, 160, 2
 EXPORTED = (
     "fwi_create", "fwi_destroy", "fwi_workspace_bytes", "fwi_rademacher", "fwi_delays", "fwi_forward",
     "fwi_gradient", "fwi_backward", "fwi_derivative", "fwi_get_tuning", "fwi_set_tuning",
-    "fwi_set_absorption",
+    "fwi_set_absorption", "fwi_set_delays",
     "fwi_timing_enable", "fwi_timing_read", "fwi_gamma_size", "fwi_gamma_gather", "fwi_gamma_scatter",
     "fwi_lbfgs_create", "fwi_lbfgs_destroy", "fwi_lbfgs_push", "fwi_lbfgs_apply", "fwi_lbfgs_count",
     "fwi_vec_axpby", "fwi_vec_clip", "fwi_vec_sqslowness", "fwi_interp_fourier", "fwi_resample_time",
@@ -113,6 +114,8 @@ def load(path: str = LIB_PATH):
     lib.fwi_set_tuning.restype = c_int
     lib.fwi_set_absorption.argtypes = [h, c_double, c_double, c_void_p, c_int32]
     lib.fwi_set_absorption.restype = c_int
+    lib.fwi_set_delays.argtypes = [h, c_int32, POINTER(c_int32)]
+    lib.fwi_set_delays.restype = c_int
     lib.fwi_gamma_size.argtypes = [h, POINTER(c_int64)]
     lib.fwi_gamma_size.restype = c_int
     lib.fwi_gamma_gather.argtypes = [h, c_void_p, c_void_p, c_void_p]

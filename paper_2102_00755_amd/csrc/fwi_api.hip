@@ -180,6 +180,7 @@ struct Layout {
   size_t partial_bytes = 0;
   size_t tables_bytes = 0;
   size_t geom_bytes = 0;
+  size_t delay_bytes = 0;    // [batch][n_src] int32 source delays
   size_t total = 0;
 };
 
@@ -210,8 +211,9 @@ Layout make_layout(const fwi_params& p, const Geometry& g) {
   L.geom_bytes = align256(((size_t)g.nlines + 1) * 4 * 4) +
                  align256(((size_t)g.n_src + g.n_rec + g.n_bnd + g.n_gam) * 2) +
                  align256(((size_t)g.n_src + g.n_rec + g.n_gam) * 4) + 4096;
+  L.delay_bytes = align256((size_t)p.batch * std::max(g.n_src, 1) * 4);
   L.total = L.slots_bytes + L.tape_bytes + L.traces_bytes + L.adj_bytes + L.ring_bytes + L.gacc_bytes +
-            L.partial_bytes + L.tables_bytes + L.geom_bytes + 256;
+            L.partial_bytes + L.tables_bytes + L.geom_bytes + L.delay_bytes + 256;
   return L;
 }
 
@@ -305,6 +307,8 @@ struct EngineBase {
   virtual int derivative(const void* in, void* out, int axis, int sign, hipStream_t st) = 0;
   // power-law absorption (Sec. 2.1); alpha0 == 0 with no field switches it off
   virtual int set_absorption(double alpha0, double y, const void* field, int tr_flip) = 0;
+  // whole-step source delays [B][n_src] (host), B = 0 switches them off
+  virtual int set_delays(int B, const int32_t* host) = 0;
   // Gamma-compact vectors: compact[k] = full[gamma voxel k] (gather) or back
   virtual int gamma_copy(const void* src, void* dst, bool gather, hipStream_t st) = 0;
   virtual long long gamma_count() const = 0;
@@ -328,7 +332,7 @@ template <typename T> struct Engine : EngineBase {
   Dims d{};
   int device = 0;
   DevBuf mem_slots, mem_tape, mem_traces, mem_adj, mem_ring, mem_gacc, mem_partial, mem_tables, mem_geom,
-      mem_slot_table, mem_flag;
+      mem_slot_table, mem_flag, mem_delay;
   Tables<T> tb{};
   LineGeom lg{};
   Slot<T>* slot_table = nullptr;  // device [2*batch]
@@ -342,6 +346,9 @@ template <typename T> struct Engine : EngineBase {
   int32_t* gam_lin = nullptr;
   int* flag = nullptr;
   int* step_counter = nullptr;   // device step index of replayed step graphs
+  int32_t* delay = nullptr;      // [batch][n_src] whole-step source delays (eq. DelaySE)
+  bool delays_on = false;
+  bool mean_out = false;         // FWI_MEAN: one averaged gradient grid
   bool use_graph = false;
   int nblk_rec = 1;
   bool tape_valid = false;
@@ -387,6 +394,8 @@ template <typename T> struct Engine : EngineBase {
     if ((rc = alloc(mem_geom, lay.geom_bytes))) return rc;
     if ((rc = alloc(mem_slot_table, sizeof(Slot<T>) * 2 * p.batch))) return rc;
     if ((rc = alloc(mem_flag, 256))) return rc;
+    if ((rc = alloc(mem_delay, lay.delay_bytes))) return rc;
+    delay = (int32_t*)mem_delay.p;
     tape = (T*)mem_tape.p;
     traces_int = (T*)mem_traces.p;
     adj = (T*)mem_adj.p;
@@ -416,6 +425,7 @@ template <typename T> struct Engine : EngineBase {
     // clear the whole workspace once so that no uninitialised value is ever read
     FWI_HIP(hipMemset(mem_slots.p, 0, lay.slots_bytes));
     FWI_HIP(hipMemset(mem_ring.p, 0, lay.ring_bytes));
+    FWI_HIP(hipMemset(mem_delay.p, 0, lay.delay_bytes));
     FWI_HIP(hipDeviceSynchronize());
     return FWI_OK;
   }
@@ -592,6 +602,7 @@ template <typename T> struct Engine : EngineBase {
     a.src_k = (T)(2.0 * p.dt / (3.0 * p.dx));
     a.c = c;
     a.ring = ring; a.gacc = gacc;
+    a.delay = delays_on ? delay : nullptr;
     return a;
   }
   int launch_x2(int mode, int B, const X2Args<T>& a, hipStream_t st) {
@@ -945,15 +956,40 @@ template <typename T> struct Engine : EngineBase {
       if ((rc = fill<T>(ring + ((size_t)b * 3 + slot) * d.n_gam, (long long)d.n_gam, (T)0, st))) return rc;
     return FWI_OK;
   }
-  // G on Gamma -> full grid, zero elsewhere
+  // G on Gamma -> full grid, zero elsewhere ([B] grids, or their mean in one
+  // grid when mean_out is set)
   int scatter_grad(int B, T* grad, hipStream_t st) {
     int rc;
+    if (mean_out) {
+      if ((rc = fill<T>(grad, (long long)d.nfield, (T)0, st))) return rc;
+      if (d.n_gam > 0) {
+        hipLaunchKernelGGL((k_grad_mean_scatter<T>), dim3((d.n_gam + 255) / 256), dim3(256), 0, st, gacc, gam_lin,
+                           d.n_gam, grad, B);
+        FWI_HIP(hipGetLastError());
+      }
+      return FWI_OK;
+    }
     if ((rc = fill<T>(grad, (long long)B * d.nfield, (T)0, st))) return rc;
     if (d.n_gam > 0) {
       hipLaunchKernelGGL((k_grad_scatter<T>), dim3((d.n_gam + 255) / 256, B), dim3(256), 0, st, gacc, gam_lin,
                          d.n_gam, d.nfield, grad, B);
       FWI_HIP(hipGetLastError());
     }
+    return FWI_OK;
+  }
+
+  int set_delays(int B, const int32_t* host) override {
+    if (B < 0 || B > p.batch) return fail(FWI_ERR_INVALID_ARG, "B outside [0, batch]");
+    if (B > 0 && !host) return fail(FWI_ERR_INVALID_ARG, "NULL delay array");
+    std::vector<int32_t> rows((size_t)p.batch * std::max(d.n_src, 1), 0);
+    for (long long i = 0; i < (long long)B * d.n_src; ++i) {
+      if (host[i] < 0 || host[i] >= p.nt) return fail(FWI_ERR_INVALID_ARG, "delay outside [0, nt)");
+      rows[i] = host[i];
+    }
+    FWI_HIP(hipSetDevice(device));
+    FWI_HIP(hipDeviceSynchronize());   // no call of this handle may be reading the table
+    FWI_HIP(hipMemcpy(delay, rows.data(), rows.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    delays_on = B > 0;
     return FWI_OK;
   }
 
@@ -992,13 +1028,14 @@ template <typename T> struct Engine : EngineBase {
       if ((rc = check_c(B, (const T*)c, st))) return rc;
     tape_valid = false;
     use_graph = (flags & FWI_GRAPH) != 0;
+    mean_out = (flags & FWI_MEAN) != 0;
     if ((rc = run_forward(B, (const T*)c, (const T*)src, w, traces_int, true, st))) return rc;
     if ((rc = run_adjoint_tr(B, (const T*)c, (const T*)obs, false, traces_int, misfit, (T*)grad,
                              (flags & FWI_TR_FINAL_STATE) != 0, st)))
       return rc;
     FWI_HIP(timer.collect(st));
     if (flags & FWI_CHECK_FINITE)
-      if ((rc = check_finite((const T*)grad, (long long)B * d.nfield, st))) return rc;
+      if ((rc = check_finite((const T*)grad, (long long)(mean_out ? 1 : B) * d.nfield, st))) return rc;
     return FWI_OK;
   }
 
@@ -1010,12 +1047,13 @@ template <typename T> struct Engine : EngineBase {
     if (!tape_valid || tape_B != B) return fail(FWI_ERR_NO_TAPE, "no saved tape for this batch size");
     FWI_HIP(hipSetDevice(device));
     use_graph = (flags & FWI_GRAPH) != 0;
+    mean_out = (flags & FWI_MEAN) != 0;
     if ((rc = run_adjoint_tr(B, (const T*)c, (const T*)resid, true, (const T*)resid, misfit, (T*)grad,
                              (flags & FWI_TR_FINAL_STATE) != 0, st)))
       return rc;
     FWI_HIP(timer.collect(st));
     if (flags & FWI_CHECK_FINITE)
-      if ((rc = check_finite((const T*)grad, (long long)B * d.nfield, st))) return rc;
+      if ((rc = check_finite((const T*)grad, (long long)(mean_out ? 1 : B) * d.nfield, st))) return rc;
     return FWI_OK;
   }
 
@@ -1264,6 +1302,11 @@ int fwi_derivative(fwi_handle* h, const void* in, void* out, int32_t axis, int32
 int fwi_set_absorption(fwi_handle* h, double alpha0, double y, const void* alpha0_field, int32_t tr_flip) {
   if (!h) return fail(FWI_ERR_INVALID_ARG, "handle is NULL");
   return h->eng->set_absorption(alpha0, y, alpha0_field, tr_flip);
+}
+
+int fwi_set_delays(fwi_handle* h, int32_t B, const int32_t* delays) {
+  if (!h) return fail(FWI_ERR_INVALID_ARG, "NULL handle");
+  return h->eng->set_delays(B, delays);
 }
 
 int fwi_get_tuning(const fwi_handle* h, fwi_tuning* out) {

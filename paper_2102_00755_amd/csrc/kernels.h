@@ -904,6 +904,7 @@ template <typename T> struct X2Args {
   const T* c;            // [B][nfield]
   const T* src_sig;      // [B][nt][n_src]
   const int8_t* w;       // [B][n_src]
+  const int32_t* delay;  // [B][n_src] whole-step source delays, or null (none)
   T* traces;             // [B][nt][n_rec]
   T* tape;               // [B][nt][n_bnd] or null
   const T* adj_src;      // [B][nt][n_rec]: a^j (reversed running sum of the residual)
@@ -1021,8 +1022,10 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx
       const int l = local_line(a.g.src_off, l0, nl, i);
       const int x = a.g.src_x[i], id = a.g.src_id[i];
       const T cv = cb[(size_t)(l0 + l) * nx + x];
-      const T val = a.src_k / cv * (T)a.w[(size_t)b * a.d.n_src + id] *
-                    a.src_sig[((size_t)b * a.d.nt + si.step) * a.d.n_src + id];
+      // delayed encoding (eq. DelaySE): source id fires its signal d_id steps late
+      const int k = a.delay ? si.step - a.delay[(size_t)b * a.d.n_src + id] : si.step;
+      const T sv = k >= 0 ? a.src_sig[((size_t)b * a.d.nt + k) * a.d.n_src + id] : (T)0;
+      const T val = a.src_k / cv * (T)a.w[(size_t)b * a.d.n_src + id] * sv;
       T* sp = reinterpret_cast<T*>(spv);
       sp[2 * ((x >> 1) * LPB + l) + (x & 1)] = val;
     }
@@ -1420,6 +1423,18 @@ __global__ void k_grad_scatter(const double* gacc, const int32_t* gam_lin, int n
   const int b = blockIdx.y;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_gam; i += gridDim.x * blockDim.x)
     grad[(size_t)b * nfield + gam_lin[i]] = (T)gacc[(size_t)b * n_gam + i];
+}
+
+// Mean of the B gradients of one batched call (averaging of independent
+// encoded realisations, Sec. 3.2): grad[gamma voxel i] = (1/B) sum_b G_b[i],
+// summed in FP64 over b = 0..B-1 in that order (deterministic), rounded once.
+template <typename T>
+__global__ void k_grad_mean_scatter(const double* gacc, const int32_t* gam_lin, int n_gam, T* grad, int B) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_gam; i += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < B; ++b) s += gacc[(size_t)b * n_gam + i];
+    grad[gam_lin[i]] = (T)(s / (double)B);
+  }
 }
 
 // flag |= 1 if any value lies outside [lo, hi] or is not finite

@@ -55,18 +55,6 @@ def delays(seed: int, n: int, tau_steps: int) -> np.ndarray:
     return out
 
 
-def delayed_signals(src_sig, delays_steps, nt_total: int) -> np.ndarray:
-    """Per-source signals [nt_total, n_src] with source i shifted by delays_steps[i]
-    (eq. DelaySE: s_i(t - d_i tau)); zero before the shift and after the end."""
-    src = np.asarray(src_sig)
-    nt, ns = src.shape
-    out = np.zeros((nt_total, ns), dtype=src.dtype)
-    for i, d in enumerate(np.asarray(delays_steps)):
-        m = max(0, min(nt, nt_total - int(d)))
-        out[int(d):int(d) + m, i] = src[:m, i]
-    return out
-
-
 def _params(shape, dx, dt, nt, c_ref, c_min, c_max, rho0, pml, pml_alpha, precision, batch):
     nz, ny, nx = shape
     p = L.FwiParams()
@@ -162,13 +150,22 @@ class Handle:
             pass
 
     # ------------------------------------------------------------------
-    def _t(self, x, shape_tail, dtype=None):
+    def _t(self, x, shape_tail, dtype=None, batch=None):
+        """x as a contiguous [B', *shape_tail] tensor on the device.  With
+        `batch` given, B' must be 1 or batch, and a leading 1 is expanded to
+        batch (one array shared by every problem): the kernels index every
+        per-problem array by the problem number, so a shorter array would be
+        read out of bounds."""
         dtype = dtype or self.dtype
         t = torch.as_tensor(x, device=self.device, dtype=dtype)
         if t.dim() == len(shape_tail):
             t = t.unsqueeze(0)
-        if tuple(t.shape[1:]) != tuple(shape_tail):
+        if t.dim() != len(shape_tail) + 1 or tuple(t.shape[1:]) != tuple(shape_tail):
             raise ValueError(f"expected [..., {shape_tail}], got {tuple(t.shape)}")
+        if batch is not None and t.shape[0] != batch:
+            if t.shape[0] != 1:
+                raise ValueError(f"leading dimension {t.shape[0]} is neither 1 nor the batch {batch}")
+            t = t.expand(batch, *shape_tail)
         return t.contiguous()
 
     def _stream(self):
@@ -178,8 +175,8 @@ class Handle:
         """Traces [B, nt, n_rec] of the encoded sources sum_i w_i s_i."""
         c = self._t(c, self.shape)
         B = c.shape[0]
-        src = self._t(src_sig, (self.nt, self.n_src))
-        w = self._t(w, (self.n_src,), torch.int8)
+        src = self._t(src_sig, (self.nt, self.n_src), batch=B)
+        w = self._t(w, (self.n_src,), torch.int8, batch=B)
         tr = torch.empty((B, self.nt, self.n_rec), device=self.device, dtype=self.dtype)
         flags = (L.FWI_SAVE_TAPE if save_tape else 0) | (L.FWI_CHECK_INPUT if check else 0)
         flags |= L.FWI_GRAPH if self.use_graph else 0
@@ -188,40 +185,45 @@ class Handle:
                                      tr.data_ptr(), flags, self._stream()), "fwi_forward")
         return tr
 
-    def gradient(self, c, src_sig, w, obs, check=False, out=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    def gradient(self, c, src_sig, w, obs, check=False, out=None, mean=False) -> Tuple[torch.Tensor, torch.Tensor]:
         """(misfit [B] float64, gradient [B, nz, ny, nx]) of the encoded TR gradient.
         check=True validates c against [c_min, c_max] and the result for
-        finiteness (both read a device flag back, so the call synchronises)."""
+        finiteness (both read a device flag back, so the call synchronises).
+        mean=True returns the mean of the B gradients as [1, nz, ny, nx]
+        (FWI_MEAN: averaged on the device in a fixed order)."""
         c = self._t(c, self.shape)
         B = c.shape[0]
-        src = self._t(src_sig, (self.nt, self.n_src))
-        w = self._t(w, (self.n_src,), torch.int8)
-        obs = self._t(obs, (self.nt, self.n_rec))
+        src = self._t(src_sig, (self.nt, self.n_src), batch=B)
+        w = self._t(w, (self.n_src,), torch.int8, batch=B)
+        obs = self._t(obs, (self.nt, self.n_rec), batch=B)
         mis = torch.empty((B,), device=self.device, dtype=torch.float64)
+        G = 1 if mean else B
         if out is not None:
-            if tuple(out.shape) != (B, *self.shape) or out.dtype != self.dtype or not out.is_contiguous():
-                raise ValueError("out must be a contiguous [B, nz, ny, nx] tensor of the handle's dtype")
+            if tuple(out.shape) != (G, *self.shape) or out.dtype != self.dtype or not out.is_contiguous():
+                raise ValueError(f"out must be a contiguous [{G}, nz, ny, nx] tensor of the handle's dtype")
             grad = out
         else:
-            grad = torch.empty((B, *self.shape), device=self.device, dtype=self.dtype)
+            grad = torch.empty((G, *self.shape), device=self.device, dtype=self.dtype)
         flags = (L.FWI_CHECK_INPUT | L.FWI_CHECK_FINITE if check else 0) | (L.FWI_GRAPH if self.use_graph else 0)
         flags |= L.FWI_TR_FINAL_STATE if self.tr_final_state else 0
+        flags |= L.FWI_MEAN if mean else 0
         self.tape_token += 1
         _check(self._lib.fwi_gradient(self._h, B, c.data_ptr(), src.data_ptr(), w.data_ptr(), obs.data_ptr(),
                                       mis.data_ptr(), grad.data_ptr(), flags, self._stream()), "fwi_gradient")
         return mis, grad
 
-    def backward(self, c, residual, check=False) -> Tuple[torch.Tensor, torch.Tensor]:
+    def backward(self, c, residual, check=False, mean=False) -> Tuple[torch.Tensor, torch.Tensor]:
         """(1/2 ||r||^2 [B], (df/dc)^T r on Gamma) using the tape of the last
         forward(save_tape=True) call with the same batch (FwiError with
-        FWI_ERR_NO_TAPE otherwise); check as in gradient()."""
+        FWI_ERR_NO_TAPE otherwise); check and mean as in gradient()."""
         c = self._t(c, self.shape)
         B = c.shape[0]
-        r = self._t(residual, (self.nt, self.n_rec))
+        r = self._t(residual, (self.nt, self.n_rec), batch=B)
         mis = torch.empty((B,), device=self.device, dtype=torch.float64)
-        grad = torch.empty((B, *self.shape), device=self.device, dtype=self.dtype)
+        grad = torch.empty((1 if mean else B, *self.shape), device=self.device, dtype=self.dtype)
         flags = (L.FWI_GRAPH if self.use_graph else 0) | (L.FWI_TR_FINAL_STATE if self.tr_final_state else 0)
         flags |= (L.FWI_CHECK_INPUT | L.FWI_CHECK_FINITE) if check else 0
+        flags |= L.FWI_MEAN if mean else 0
         _check(self._lib.fwi_backward(self._h, B, c.data_ptr(), r.data_ptr(), mis.data_ptr(), grad.data_ptr(),
                                       flags, self._stream()), "fwi_backward")
         return mis, grad
@@ -267,6 +269,21 @@ class Handle:
         # error above the previous field stays in use and stays referenced
         self._alpha0_field = f
         self.tape_token += 1
+
+    def set_delays(self, delays=None) -> None:
+        """Delayed source encoding (eq. DelaySE): delays [B, n_src] (or [n_src]
+        for B = 1) in whole steps, each in [0, nt); None switches delays off.
+        The library shifts the injected signals; signals stay unshifted."""
+        if delays is None:
+            _check(self._lib.fwi_set_delays(self._h, 0, None), "fwi_set_delays")
+            return
+        d = np.ascontiguousarray(np.asarray(delays, dtype=np.int32))
+        if d.ndim == 1:
+            d = d[None, :]
+        if d.ndim != 2 or d.shape[1] != self.n_src:
+            raise ValueError(f"expected delays [B, {self.n_src}], got {d.shape}")
+        _check(self._lib.fwi_set_delays(self._h, int(d.shape[0]), d.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
+               "fwi_set_delays")
 
     def timing_enable(self, every: int) -> None:
         """Sample every `every`-th time step's pass launches with HIP events."""

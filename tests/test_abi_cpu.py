@@ -76,12 +76,9 @@ def test_delays_bit_exact_with_oracle(seed, tau):
         assert abs(got.mean() / tau - 0.5) < 0.05     # d_i ~ U[0,1)
 
 
-def test_delayed_signals_shift():
-    from paper_2102_00755_amd.fwi import delayed_signals
-    S = np.arange(12, dtype=np.float64).reshape(6, 2) + 1
-    out = delayed_signals(S, [0, 3], 8)
-    assert np.array_equal(out[:6, 0], S[:, 0]) and np.all(out[6:, 0] == 0)
-    assert np.all(out[:3, 1] == 0) and np.array_equal(out[3:8, 1], S[:5, 1])
+def test_set_delays_rejects_null_handle():
+    L, lib = _lib()
+    assert lib.fwi_set_delays(None, 0, None) == L.FWI_ERR_INVALID_ARG
 
 
 def test_set_tuning_rejects_null_handle_and_bad_values():

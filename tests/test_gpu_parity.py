@@ -136,6 +136,35 @@ def test_batched_equals_individual():
     h3.close()
 
 
+def test_batched_call_broadcasts_shared_inputs():
+    # one unbatched signal / weight / data array with a batched c is shared by
+    # every problem (expanded by the binding) and gives what the explicitly
+    # repeated arrays give; a leading dimension that is neither 1 nor B is
+    # rejected before anything is launched
+    shape = SHAPES[0]
+    probs = [make_small(shape=shape, nt=30, n_src=2, n_rec=12, layer=2, seed=s, precision=4) for s in (31, 32)]
+    base = probs[0]
+    h = handle(base, 4, batch=2)
+    c = torch.from_numpy(np.stack([p.c_eval for p in probs]))
+    S = torch.from_numpy(base.src_signals())
+    w = torch.from_numpy(oracle.rademacher(7, base.n_src))
+    obs = torch.from_numpy(random_traces(base.nt, base.n_rec, seed=5, scale=1e-3))
+    m_sh, g_sh = h.gradient(c, S, w, obs)
+    m_ex, g_ex = h.gradient(c, S.expand(2, *S.shape), w.expand(2, *w.shape), obs.expand(2, *obs.shape))
+    assert torch.equal(g_sh.cpu(), g_ex.cpu()) and torch.equal(m_sh.cpu(), m_ex.cpu())
+    t_sh = h.forward(c, S, w)
+    t_ex = h.forward(c, S.expand(2, *S.shape), w.expand(2, *w.shape))
+    assert torch.equal(t_sh.cpu(), t_ex.cpu())
+    c3 = torch.from_numpy(np.stack([p.c_eval for p in probs] + [base.c_eval]))
+    with pytest.raises(ValueError):
+        h.gradient(c3[:2], S.expand(3, *S.shape), w, obs)
+    with pytest.raises(ValueError):
+        h.forward(c3[:2], S, w.expand(3, *w.shape))
+    with pytest.raises(ValueError):
+        h.backward(c3[:2], obs.expand(3, *obs.shape))
+    h.close()
+
+
 @pytest.mark.parametrize("precision,tol", [(8, 1e-9), (4, 1e-3)])
 def test_tr_gradient_from_final_state_matches_oracle(precision, tol):
     # reading 11: TR started from (rho^N, -v^{N+1/2}) instead of the zero interior

@@ -374,3 +374,40 @@ def test_delayed_encoding_removes_cross_talk():
     e0, e1, e2 = gap(0), gap(160), gap(240)
     assert e0 > e1 > e2
     assert e2 < 1e-2 and e0 > 20 * e2
+
+
+def test_uniform_delay_shifts_traces_exactly():
+    # eq. DelaySE with one delay d for every source: the scheme is the same
+    # operation at every step and starts from zero, so the traces are the
+    # undelayed traces d steps later, bit for bit, and zero before
+    prob = sc.make_small(shape=(16, 16, 16), pml=4, nt=40, n_src=2, n_rec=8, layer=2)
+    sch = ks.scheme_for(prob)
+    S = prob.src_signals()
+    w = ks.rademacher(prob.enc_seed, prob.n_src)
+    d = 7
+    f0 = ks.forward(sch, prob.c_true, prob.src_ijk, S, w, prob.rec_ijk, prob.nt)["traces"]
+    Sd = ks.delayed_signals(S, [d] * prob.n_src, prob.nt + d)
+    f1 = ks.forward(sch, prob.c_true, prob.src_ijk, Sd, w, prob.rec_ijk, prob.nt + d)["traces"]
+    assert np.all(f1[:d] == 0)
+    assert np.array_equal(f1[d:], f0)
+
+
+def test_per_source_delays_superpose():
+    # linearity and time invariance: the delayed encoded traces are the sum of
+    # each source's own traces shifted by its delay and weighted by w_i
+    prob = sc.make_small(shape=(16, 16, 16), pml=4, nt=30, n_src=3, n_rec=8, layer=2)
+    sch = ks.scheme_for(prob)
+    S = prob.src_signals()
+    w = np.array([1, -1, 1], dtype=np.int8)
+    d = [0, 5, 11]
+    N = prob.nt + 11
+    enc = ks.forward(sch, prob.c_true, prob.src_ijk, ks.delayed_signals(S, d, N), w, prob.rec_ijk, N)["traces"]
+    want = np.zeros_like(enc)
+    Sp = np.zeros((N, 3))
+    Sp[:prob.nt] = S
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = 1.0
+        fi = ks.forward(sch, prob.c_true, prob.src_ijk, Sp[:N - d[i]], e, prob.rec_ijk, N - d[i])["traces"]
+        want[d[i]:] += w[i] * fi
+    assert rel(enc, want) < 1e-12
