@@ -292,6 +292,22 @@ int fwi_lbfgs_push(fwi_lbfgs* L, const void* s, const void* y, fwi_stream_t stre
  * FP64 in a fixed order; their scalars stay in device memory. */
 int fwi_lbfgs_apply(fwi_lbfgs* L, const void* g, void* r, double h0, fwi_stream_t stream);
 
+/* fwi_lbfgs_apply for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same two-loop recursion, bit-identical results, but its scratch (the
+ * alpha_j, the second-loop coefficient and the dot-product partial sums) is
+ * a static device array of the library, sized for FWI_NOALLOC_MAX_PAIRS
+ * pairs, instead of memory owned by the history; the call makes no
+ * allocation (no hipMalloc, hipFree or allocating library routine).  The
+ * history itself still comes from fwi_lbfgs_create (set-up time).
+ * Each device has ONE such array, shared by every call on that device and
+ * kept until the process ends: calls of this entry point that overlap on one
+ * device (on different streams or threads) race and give wrong results; order
+ * them on one stream.  FWI_ERR_INVALID_ARG (nothing launched) for a NULL
+ * argument or a history of more than FWI_NOALLOC_MAX_PAIRS pairs (its m). */
+enum { FWI_NOALLOC_MAX_PAIRS = 256 };
+int fwi_lbfgs_apply_noalloc(fwi_lbfgs* L, const void* g, void* r, double h0, fwi_stream_t stream);
+
 /* Number of stored pairs (host bookkeeping, no device access). */
 int fwi_lbfgs_count(const fwi_lbfgs* L, int32_t* count);
 

@@ -30,6 +30,8 @@ FWI_TR_FINAL_STATE = 8
 FWI_GRAPH = 16
 FWI_MEAN = 32
 
+FWI_NOALLOC_MAX_PAIRS = 256   # static scratch of fwi_lbfgs_apply_noalloc
+
 SUPPORTED_LENGTHS = (8, 12, 16, 24, 32, 40, 48, 56, 64, 80, 96, 112, 128, 160, 224, 256, 448)
 
 # every symbol declared in include/fwi.h
@@ -38,7 +40,8 @@ EXPORTED = (
     "fwi_gradient", "fwi_backward", "fwi_derivative", "fwi_get_tuning", "fwi_set_tuning",
     "fwi_set_absorption", "fwi_set_delays",
     "fwi_timing_enable", "fwi_timing_read", "fwi_gamma_size", "fwi_gamma_gather", "fwi_gamma_scatter",
-    "fwi_lbfgs_create", "fwi_lbfgs_destroy", "fwi_lbfgs_push", "fwi_lbfgs_apply", "fwi_lbfgs_count",
+    "fwi_lbfgs_create", "fwi_lbfgs_destroy", "fwi_lbfgs_push", "fwi_lbfgs_apply", "fwi_lbfgs_apply_noalloc",
+    "fwi_lbfgs_count",
     "fwi_vec_axpby", "fwi_vec_clip", "fwi_vec_sqslowness", "fwi_interp_fourier", "fwi_resample_time",
     "fwi_status_string", "fwi_last_error",
 )
@@ -130,6 +133,8 @@ def load(path: str = LIB_PATH):
     lib.fwi_lbfgs_push.restype = c_int
     lib.fwi_lbfgs_apply.argtypes = [c_void_p, c_void_p, c_void_p, c_double, c_void_p]
     lib.fwi_lbfgs_apply.restype = c_int
+    lib.fwi_lbfgs_apply_noalloc.argtypes = [c_void_p, c_void_p, c_void_p, c_double, c_void_p]
+    lib.fwi_lbfgs_apply_noalloc.restype = c_int
     lib.fwi_lbfgs_count.argtypes = [c_void_p, POINTER(c_int32)]
     lib.fwi_lbfgs_count.restype = c_int
     lib.fwi_vec_axpby.argtypes = [c_int64, c_double, c_void_p, c_double, c_void_p, c_int32, c_void_p]

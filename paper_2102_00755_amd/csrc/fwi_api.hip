@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1152,13 +1153,23 @@ namespace {
 
 int vec_blocks(long long n) { return (int)std::min<long long>((n + 255) / 256, 8192); }
 
+// Scratch of one two-loop recursion: alpha[m], the coefficient of the second
+// loop and the dot-product partial sums (part[RED_BLOCKS]).  fwi_lbfgs_apply
+// takes it from the history's own allocation, fwi_lbfgs_apply_noalloc from
+// the library's static device array.
+struct LbfgsScratch {
+  double* alpha;
+  double* coef;
+  double* part;
+};
+
 template <typename T>
-int lbfgs_dot(fwi_lbfgs* L, const void* a, const void* b, int mode, const double* rho, const double* alpha,
-              double* out, hipStream_t st) {
+int lbfgs_dot(fwi_lbfgs* L, double* part, const void* a, const void* b, int mode, const double* rho,
+              const double* alpha, double* out, hipStream_t st) {
   hipLaunchKernelGGL((k_dot_partial<T>), dim3(RED_BLOCKS), dim3(RED_NT), 0, st, (const T*)a, (const T*)b, L->n,
-                     L->part());
+                     part);
   FWI_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(RED_NT), 0, st, L->part(), RED_BLOCKS, mode, rho, alpha, out);
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(RED_NT), 0, st, part, RED_BLOCKS, mode, rho, alpha, out);
   FWI_HIP(hipGetLastError());
   return FWI_OK;
 }
@@ -1175,28 +1186,31 @@ template <typename T> int lbfgs_push(fwi_lbfgs* L, const void* s, const void* y,
   const size_t bytes = (size_t)L->n * sizeof(T);
   FWI_HIP(hipMemcpyAsync(L->vec(L->S, slot), s, bytes, hipMemcpyDeviceToDevice, st));
   FWI_HIP(hipMemcpyAsync(L->vec(L->Y, slot), y, bytes, hipMemcpyDeviceToDevice, st));
-  return lbfgs_dot<T>(L, L->vec(L->Y, slot), L->vec(L->S, slot), 1, nullptr, nullptr, L->rho() + slot, st);
+  return lbfgs_dot<T>(L, L->part(), L->vec(L->Y, slot), L->vec(L->S, slot), 1, nullptr, nullptr, L->rho() + slot,
+                     st);
 }
 
-template <typename T> int lbfgs_apply(fwi_lbfgs* L, const void* g, void* r, double h0, hipStream_t st) {
+template <typename T>
+int lbfgs_apply(fwi_lbfgs* L, const LbfgsScratch& w, const void* g, void* r, double h0, hipStream_t st) {
   const size_t bytes = (size_t)L->n * sizeof(T);
   if (g != r) FWI_HIP(hipMemcpyAsync(r, g, bytes, hipMemcpyDeviceToDevice, st));
   const int nb = vec_blocks(L->n);
   int rc;
   for (int j = L->count - 1; j >= 0; --j) {   // newest to oldest: alpha_j = rho_j s_j^T q, q -= alpha_j y_j
     const int slot = (L->head + j) % L->m;
-    if ((rc = lbfgs_dot<T>(L, L->vec(L->S, slot), r, 2, L->rho() + slot, nullptr, L->alpha() + slot, st))) return rc;
+    if ((rc = lbfgs_dot<T>(L, w.part, L->vec(L->S, slot), r, 2, L->rho() + slot, nullptr, w.alpha + slot, st)))
+      return rc;
     hipLaunchKernelGGL((k_axpy_dev<T>), dim3(nb), dim3(256), 0, st, (T*)r, (const T*)L->vec(L->Y, slot),
-                       L->alpha() + slot, -1.0, L->n);
+                       w.alpha + slot, -1.0, L->n);
     FWI_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL((k_axpby<T>), dim3(nb), dim3(256), 0, st, L->n, (T)0, (const T*)nullptr, (T)h0, (T*)r);
   FWI_HIP(hipGetLastError());
   for (int j = 0; j < L->count; ++j) {        // oldest to newest: r += (alpha_j - rho_j y_j^T r) s_j
     const int slot = (L->head + j) % L->m;
-    if ((rc = lbfgs_dot<T>(L, L->vec(L->Y, slot), r, 3, L->rho() + slot, L->alpha() + slot, L->coef(), st)))
+    if ((rc = lbfgs_dot<T>(L, w.part, L->vec(L->Y, slot), r, 3, L->rho() + slot, w.alpha + slot, w.coef, st)))
       return rc;
-    hipLaunchKernelGGL((k_axpy_dev<T>), dim3(nb), dim3(256), 0, st, (T*)r, (const T*)L->vec(L->S, slot), L->coef(),
+    hipLaunchKernelGGL((k_axpy_dev<T>), dim3(nb), dim3(256), 0, st, (T*)r, (const T*)L->vec(L->S, slot), w.coef,
                        1.0, L->n);
     FWI_HIP(hipGetLastError());
   }
@@ -1204,6 +1218,42 @@ template <typename T> int lbfgs_apply(fwi_lbfgs* L, const void* g, void* r, doub
 }
 
 bool prec_ok(int p) { return p == 4 || p == 8; }
+
+}  // namespace
+
+// Static scratch of fwi_lbfgs_apply_noalloc: alpha[FWI_NOALLOC_MAX_PAIRS], the
+// second-loop coefficient (padded to 8 doubles) and the RED_BLOCKS partial
+// sums of each dot product.  Every device holds its own copy until the
+// process ends; host code reaches it only through the address that
+// hipGetSymbolAddress returned on that device (noalloc_scratch), never
+// through the array's name.  Every value is written before it is read within
+// one call, so nothing needs clearing between calls.
+constexpr int kNoallocCoefOff = FWI_NOALLOC_MAX_PAIRS;
+constexpr int kNoallocPartOff = FWI_NOALLOC_MAX_PAIRS + 8;
+static __device__ __align__(256) double scratch[kNoallocPartOff + RED_BLOCKS];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (resolved once per device with that
+// device current, then cached).  Leaves `device` current.
+int noalloc_scratch(int device, double** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return fail(FWI_ERR_INVALID_ARG, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    FWI_HIP(hipSetDevice(device));
+    void* ptr = nullptr;
+    FWI_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(FWI_ERR_HIP, "hipGetSymbolAddress returned a null address for the static scratch");
+    g_scratch_dev[device] = (double*)ptr;
+  }
+  *out = g_scratch_dev[device];
+  return FWI_OK;
+}
 
 }  // namespace
 
@@ -1418,6 +1468,9 @@ int fwi_lbfgs_create(int64_t n, int32_t m, int32_t precision, int32_t device, fw
   std::unique_ptr<fwi_lbfgs> L(new fwi_lbfgs());
   L->precision = precision; L->device = device; L->m = m; L->n = n;
   FWI_HIP(hipSetDevice(device));
+  double* scratch_ptr = nullptr;   // resolve the static scratch of fwi_lbfgs_apply_noalloc on this device
+  int rc = noalloc_scratch(device, &scratch_ptr);
+  if (rc) return rc;
   const size_t vb = (size_t)m * n * precision;
   if (hipMalloc(&L->S, vb) != hipSuccess || hipMalloc(&L->Y, vb) != hipSuccess ||
       hipMalloc((void**)&L->sc, (2 * (size_t)m + 1 + RED_BLOCKS) * sizeof(double)) != hipSuccess) {
@@ -1449,8 +1502,23 @@ int fwi_lbfgs_push(fwi_lbfgs* L, const void* s, const void* y, fwi_stream_t stre
 int fwi_lbfgs_apply(fwi_lbfgs* L, const void* g, void* r, double h0, fwi_stream_t stream) {
   if (!L || !g || !r) return fail(FWI_ERR_INVALID_ARG, "bad arguments");
   FWI_HIP(hipSetDevice(L->device));
-  return L->precision == 4 ? lbfgs_apply<float>(L, g, r, h0, (hipStream_t)stream)
-                           : lbfgs_apply<double>(L, g, r, h0, (hipStream_t)stream);
+  const LbfgsScratch w{L->alpha(), L->coef(), L->part()};
+  return L->precision == 4 ? lbfgs_apply<float>(L, w, g, r, h0, (hipStream_t)stream)
+                           : lbfgs_apply<double>(L, w, g, r, h0, (hipStream_t)stream);
+}
+
+int fwi_lbfgs_apply_noalloc(fwi_lbfgs* L, const void* g, void* r, double h0, fwi_stream_t stream) {
+  if (!L || !g || !r) return fail(FWI_ERR_INVALID_ARG, "bad arguments");
+  if (L->m > FWI_NOALLOC_MAX_PAIRS)
+    return fail(FWI_ERR_INVALID_ARG, "history of " + std::to_string(L->m) + " pairs exceeds the " +
+                                         std::to_string((int)FWI_NOALLOC_MAX_PAIRS) +
+                                         " pairs of fwi_lbfgs_apply_noalloc's static scratch");
+  double* sp = nullptr;
+  const int rc = noalloc_scratch(L->device, &sp);   // leaves L->device current
+  if (rc) return rc;
+  const LbfgsScratch w{sp, sp + kNoallocCoefOff, sp + kNoallocPartOff};
+  return L->precision == 4 ? lbfgs_apply<float>(L, w, g, r, h0, (hipStream_t)stream)
+                           : lbfgs_apply<double>(L, w, g, r, h0, (hipStream_t)stream);
 }
 
 int fwi_lbfgs_count(const fwi_lbfgs* L, int32_t* count) {

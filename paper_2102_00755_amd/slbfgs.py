@@ -79,6 +79,13 @@ class LbfgsHistory:
         _check(self.ops.lib.fwi_lbfgs_apply(self._h, _ptr(g), _ptr(r), float(h0), self.ops._st()), "fwi_lbfgs_apply")
         return r
 
+    def apply_noalloc(self, g: torch.Tensor, r: torch.Tensor, h0: float) -> torch.Tensor:
+        """r <- H g through fwi_lbfgs_apply_noalloc (no device allocation; the
+        library's static scratch, shared by every such call on the device)."""
+        _check(self.ops.lib.fwi_lbfgs_apply_noalloc(self._h, _ptr(g), _ptr(r), float(h0), self.ops._st()),
+               "fwi_lbfgs_apply_noalloc")
+        return r
+
     def count(self) -> int:
         c = ctypes.c_int32()
         _check(self.ops.lib.fwi_lbfgs_count(self._h, ctypes.byref(c)), "fwi_lbfgs_count")
