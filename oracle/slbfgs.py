@@ -3,25 +3,25 @@
 TEST INFRASTRUCTURE, NOT PRODUCT CODE (see oracle/__init__.py).
 
 Minimises an energy J(u) given only an estimator g(u, i) -> (F, G) of
-(J(u), grad J(u)) whose stochastic approximation is fixed by the iteration
-index i (both evaluations of one iteration use the same approximation, so
-that the curvature pair (s, y) they produce is consistent).  Per iteration:
+(J(u), grad J(u)) whose stochastic approximation is fixed by the index i.
+The method is built from three parts:
 
-    F_u, G_u <- g(u, i)
-    z   <- -H_k G_u                                (two-loop recursion)
-    F_z, G_z <- g(u + nu z, i)                     (no line search)
-    S <- [S, nu z], Y <- [Y, G_z - G_u]            (keep the last m_h pairs)
-    z   <- z - H_k G_z                             (with the updated pairs)
-    u   <- clip(u + nu z, u_min, u_max)            (projection)
-    J_i <- min(F_u, F_z)
-    averaging of the iterates with weights w(i) (paper: i^3), switched on
-    after the first increase of the energy estimate J_i > J_{i-1}; the
-    returned estimate is the weighted average once it is on, else u.
+* ``LbfgsMemory``: the last m_h curvature pairs (s, y) and the product of
+  their L-BFGS inverse Hessian with a vector, initial matrix h0 I (Nocedal &
+  Wright, Numerical Optimization, 2nd ed., Algorithm 7.4).  The paper gives
+  the initial matrix as an input; a scalar multiple of the identity is the
+  reading here.
+* ``quasi_newton_step``: one step with a fixed approximation i.  Both
+  estimator calls of the step use the same i, so the pair they produce
+  (the step taken and the change of the gradient) is consistent; the pair
+  enters the memory before the direction is corrected with the gradient at
+  the trial point.  No line search: the step length is nu.
+* ``IterateAverage``: the returned estimate, the plain iterate until the
+  energy estimate first increases, afterwards the running mean of the later
+  iterates weighted by w(i) (the paper: i^3).
 
-H_k is the L-BFGS inverse Hessian of the stored pairs with the initial
-matrix H_0 = h0 I (Nocedal & Wright, Numerical Optimization, 2nd ed.,
-Algorithm 7.4).  The paper gives H_0 as an input; h0 is that input here
-(parity reading: a scalar multiple of the identity).
+``slbfgs`` composes them with the projection onto [u_min, u_max] and the
+energy estimate min(F at u, F at the trial point) of each step.
 """
 
 from __future__ import annotations
@@ -61,48 +61,85 @@ def dense_inverse_hessian(S, Y, h0: float, n: int) -> np.ndarray:
     return H
 
 
+class LbfgsMemory:
+    """The last m_h pairs (s, y), oldest first, and H v for their L-BFGS
+    inverse Hessian with H_0 = h0 I."""
+
+    def __init__(self, m_h: int, h0: float):
+        self.m_h = int(m_h)
+        self.h0 = float(h0)
+        self.S: List[np.ndarray] = []
+        self.Y: List[np.ndarray] = []
+
+    def push(self, s: np.ndarray, y: np.ndarray) -> None:
+        self.S.append(np.asarray(s, dtype=np.float64))
+        self.Y.append(np.asarray(y, dtype=np.float64))
+        if len(self.S) > self.m_h:
+            del self.S[0], self.Y[0]
+
+    def apply(self, v: np.ndarray) -> np.ndarray:
+        return two_loop(v, self.S, self.Y, self.h0)
+
+
+def quasi_newton_step(g: Callable[[np.ndarray, int], Tuple[float, np.ndarray]], u: np.ndarray, i: int,
+                      memory: LbfgsMemory, nu: float) -> Tuple[np.ndarray, float]:
+    """One stochastic quasi-Newton step of length nu with approximation i of
+    the estimator (App. D): the quasi-Newton direction d = -H G at u, the
+    estimator at the trial point u + nu d, the pair (nu d, G_trial - G) added
+    to the memory, the direction corrected by -H G_trial with the updated
+    memory.  Returns (u + nu d before any projection, min of the two energy
+    values)."""
+    F_at_u, G_at_u = g(u, i)
+    d = -memory.apply(G_at_u)
+    F_trial, G_trial = g(u + nu * d, i)
+    memory.push(nu * d, np.asarray(G_trial, dtype=np.float64) - np.asarray(G_at_u, dtype=np.float64))
+    d = d - memory.apply(G_trial)
+    return u + nu * d, min(F_at_u, F_trial)
+
+
+class IterateAverage:
+    """Estimate returned after each step: the iterate itself until the energy
+    estimate increases for the first time, then the w(i)-weighted mean of the
+    iterates of the following steps (App. D)."""
+
+    def __init__(self, weight: Callable[[int], float]):
+        self.weight = weight
+        self.on = False
+        self.total = None
+        self.wsum = 0.0
+        self.J_last = np.inf
+
+    def update(self, i: int, u: np.ndarray, J: float) -> np.ndarray:
+        if self.on:
+            wi = self.weight(i)
+            self.total = wi * u if self.total is None else self.total + wi * u
+            self.wsum += wi
+            est = self.total / self.wsum
+        else:
+            self.on = J > self.J_last
+            est = u.copy()
+        self.J_last = J
+        return est
+
+
 def slbfgs(g: Callable[[np.ndarray, int], Tuple[float, np.ndarray]], u0: np.ndarray, *, nu: float,
            n_evals: int, m_h: int = 64, h0: float = 1.0, u_min=-np.inf, u_max=np.inf,
            weight: Callable[[int], float] = lambda i: float(i) ** 3, history: bool = False):
-    """Algorithm 2 without line search.  Returns (u_hat, J_list[, iterates])."""
+    """Algorithm 2 without line search: steps i = 1, 2, ... until n_evals
+    estimator calls (two per step) are spent.  Returns (u_hat, [J_i][, the
+    estimate after each step])."""
     u = np.array(u0, dtype=np.float64)
-    u_bar = np.zeros_like(u)
-    w_bar = 0.0
-    J_prev = np.inf
-    S: List[np.ndarray] = []
-    Y: List[np.ndarray] = []
-    averaging = False
-    n_evl = 0
-    i = 0
-    Js = []
+    memory = LbfgsMemory(m_h, h0)
+    average = IterateAverage(weight)
+    Js, its = [], []
     u_hat = u.copy()
-    its = []
-    while n_evl < n_evals:
+    i = 0
+    while 2 * i < n_evals:
         i += 1
-        F_u, G_u = g(u, i)
-        n_evl += 1
-        z = -two_loop(G_u, S, Y, h0)
-        F_z, G_z = g(u + nu * z, i)
-        n_evl += 1
-        S.append(nu * z)
-        Y.append(np.asarray(G_z, dtype=np.float64) - np.asarray(G_u, dtype=np.float64))
-        if len(S) > m_h:
-            S.pop(0)
-            Y.pop(0)
-        z = z - two_loop(G_z, S, Y, h0)
-        u = u + nu * z
+        u, J = quasi_newton_step(g, u, i, memory, nu)
         u = np.maximum(np.minimum(u, u_max), u_min)
-        J_i = min(F_u, F_z)
-        if averaging:
-            u_bar = u_bar + weight(i) * u
-            w_bar = w_bar + weight(i)
-            u_hat = u_bar / w_bar
-        else:
-            if J_i > J_prev:
-                averaging = True
-            u_hat = u.copy()
-        J_prev = J_i
-        Js.append(J_i)
+        u_hat = average.update(i, u, J)
+        Js.append(J)
         if history:
             its.append(u_hat.copy())
     return (u_hat, Js, its) if history else (u_hat, Js)

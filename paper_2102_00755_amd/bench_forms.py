@@ -15,11 +15,13 @@ batched : 16 independent Rademacher-encoded TR gradients on 128^3 (phantom
           Mcell-steps/s and per-solve latency of both.
 serve   : Poisson-arriving forward / gradient requests (50/50) over the grid
           levels 96^3 @ 1.0 mm (300 steps), 160^3 @ 0.75 mm (600) and
-          224x224x112 @ 0.5 mm (1200), admitted by HBM footprint; the arrival
-          rate is set to ~80 % of the measured single-stream capacity; each
-          level uses the autotuner's tile widths;
-          reports p50/p99 latency and Mcell-steps/s against the same requests
-          solved one at a time.
+          224x224x112 @ 0.5 mm (1200), admitted by HBM footprint, waiting
+          requests of one level and kind grouped into batched calls of up to
+          --serve-batch; the arrival rate is set to each of --loads times the
+          measured single-stream capacity (default 0.8 and 2.0); each level
+          uses the autotuner's tile widths; reports p50/p99 latency,
+          Mcell-steps/s and the mean requests per call against the same
+          requests solved one at a time.
 lbfgs   : the SLBFGS two-loop recursion (64 pairs) and pair push at |Gamma| of
           the full workload, with their algorithmic bandwidth.
 multigrid: grid transfers between the 1 mm and 0.5 mm levels of the full box.
@@ -38,6 +40,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import sys
 import tempfile
 import time
 
@@ -161,33 +164,52 @@ def serve(args) -> dict:
             hs[lv].gradient(c, s, w, obs[lv])
         torch.cuda.synchronize()
         solo_lat.append(time.perf_counter() - t1)
+        if len(solo_lat) % 25 == 0:
+            print(json.dumps({"solo_done": len(solo_lat)}), file=sys.stderr, flush=True)
     t_solo = time.perf_counter() - t0
     for h in hs.values():
         h.close()
     work = sum(probs[lv].n_cells * probs[lv].nt * (3 if k == "gradient" else 1) for k, lv, *_ in reqs)
-    rate = 0.8 * len(reqs) / t_solo                # arrivals per second
-    gaps = rng.exponential(1.0 / rate, size=len(reqs))
-    budget = int(args.budget_gb * 2 ** 30)
-    srv = Server(levels, budget_bytes=budget, max_inflight=args.inflight)
-    futs = []
-    t_start = time.perf_counter()
-    for (kind, lv, c, s, w), gap in zip(reqs, gaps):
-        time.sleep(gap)
-        futs.append(srv.submit(kind, lv, c, s, w, obs[lv] if kind == "gradient" else None))
-    for f in futs:
-        f.result()
-    st = srv.stats()
-    srv.close()
-    return {
+    out = {
         "form": "serve", "tuning": {lv.name: lv.tuning for lv in levels}, "requests": len(reqs),
-        "levels": names, "arrival_rate_per_s": rate,
-        "served_Mcell_steps_per_s": st["Mcell-steps/s"], "served_p50_ms": st["p50_ms"],
-        "served_p99_ms": st["p99_ms"], "solo_Mcell_steps_per_s": work / t_solo / 1e6,
+        "levels": names, "solo_Mcell_steps_per_s": work / t_solo / 1e6,
         "solo_p50_ms": float(np.percentile(np.array(solo_lat) * 1e3, 50)),
         "solo_p99_ms": float(np.percentile(np.array(solo_lat) * 1e3, 99)),
-        "inflight": args.inflight, "handles": st["handles"], "device_bytes": st["device_bytes"],
-        "wall_s": time.perf_counter() - t_start,
+        "inflight": args.inflight, "batch_per_call": args.serve_batch, "served": [],
     }
+    budget = int(args.budget_gb * 2 ** 30)
+    for lv in levels:
+        lv.batch = args.serve_batch
+    for load in args.loads:
+        # Poisson arrivals at `load` times the single-stream capacity
+        rate = load * len(reqs) / t_solo
+        gaps = np.random.default_rng(40).exponential(1.0 / rate, size=len(reqs))
+        srv = Server(levels, budget_bytes=budget, max_inflight=args.inflight)
+        for n in names:      # warm-up: the resident handles of every level
+            p = probs[n]
+            srv.submit("forward", n, torch.from_numpy(p.c_eval), torch.from_numpy(p.src_signals()),
+                       torch.from_numpy(fwi.rademacher(1, p.n_src))).result()
+        srv.reset_stats()
+        futs = []
+        t_start = time.perf_counter()
+        for k, ((kind, lv, c, s, w), gap) in enumerate(zip(reqs, gaps)):
+            time.sleep(gap)
+            futs.append(srv.submit(kind, lv, c, s, w, obs[lv] if kind == "gradient" else None))
+            if (k + 1) % 50 == 0:
+                print(json.dumps({"load": load, "submitted": k + 1}), file=sys.stderr, flush=True)
+        for k, f in enumerate(futs):
+            f.result()
+            if (k + 1) % 25 == 0:
+                print(json.dumps({"load": load, "served_done": k + 1}), file=sys.stderr, flush=True)
+        st = srv.stats()
+        srv.close()
+        out["served"].append({
+            "offered_load": load, "arrival_rate_per_s": rate,
+            "Mcell_steps_per_s": st["Mcell-steps/s"], "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+            "calls": st["calls"], "mean_batch": st["mean_batch"], "handles": st["handles"],
+            "device_bytes": st["device_bytes"], "wall_s": time.perf_counter() - t_start,
+        })
+    return out
 
 
 def lbfgs(args) -> dict:
@@ -337,6 +359,9 @@ def main():
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--inflight", type=int, default=4)
     ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-batch", type=int, default=4, help="requests per batched call of a served level")
+    ap.add_argument("--loads", type=float, nargs="+", default=[0.8, 2.0],
+                    help="offered loads of the served trace, in units of the single-stream capacity")
     ap.add_argument("--n", type=int, default=4954176)
     ap.add_argument("--m", type=int, default=64)
     args = ap.parse_args()

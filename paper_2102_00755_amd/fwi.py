@@ -239,18 +239,20 @@ class Handle:
         return out
 
     # ------------------------------------------------------------------
+    TUNING_FIELDS = ("y_tile_bytes", "zm_tile_bytes", "zp_tile_bytes")
+
     @property
     def tuning(self) -> dict:
         """Launch tuning: {'y_tile_bytes', 'zm_tile_bytes', 'zp_tile_bytes'} (64 or 128)."""
         t = L.FwiTuning()
         _check(self._lib.fwi_get_tuning(self._h, ctypes.byref(t)), "fwi_get_tuning")
-        return {"y_tile_bytes": t.y_tile_bytes, "zm_tile_bytes": t.zm_tile_bytes, "zp_tile_bytes": t.zp_tile_bytes}
+        return {f: int(getattr(t, f)) for f in self.TUNING_FIELDS}
 
     @tuning.setter
     def tuning(self, value: dict) -> None:
         cur = self.tuning
         cur.update(value)
-        t = L.FwiTuning(int(cur["y_tile_bytes"]), int(cur["zm_tile_bytes"]), int(cur["zp_tile_bytes"]))
+        t = L.FwiTuning(*(int(cur[f]) for f in self.TUNING_FIELDS))
         _check(self._lib.fwi_set_tuning(self._h, ctypes.byref(t)), "fwi_set_tuning")
 
     def set_absorption(self, alpha0=0.0, y=1.5, field=None, tr_flip=True) -> None:

@@ -176,58 +176,91 @@ class EncodedEstimator:
         return float(mis[0])
 
 
+class _StepBuffers:
+    """Device vectors one quasi-Newton step works in."""
+
+    def __init__(self, est: EncodedEstimator):
+        self.d, self.trial, self.s, self.y = est.empty(), est.empty(), est.empty(), est.empty()
+        self.G_u, self.G_trial, self.r = est.empty(), est.empty(), est.empty()
+
+
+def quasi_newton_step(est: EncodedEstimator, u: torch.Tensor, i: int, hist: LbfgsHistory, nu: float, h0: float,
+                      buf: _StepBuffers) -> float:
+    """One stochastic quasi-Newton step of length nu with the encoding of
+    iteration i (App. D), in place on u: the direction d = -H G at u, the
+    estimator at the trial point u + nu d, the pair (nu d, G_trial - G) pushed
+    to the history, the direction corrected by -H G_trial with the updated
+    history, u <- u + nu d.  Returns the energy estimate, the smaller of the
+    two misfits.  Both estimator calls use encoding i, so the pair is
+    consistent."""
+    ops = est.ops
+    F_u = est(u, i, buf.G_u)
+    hist.apply(buf.G_u, buf.d, h0)
+    ops.axpby(0.0, None, -1.0, buf.d)                 # d = -H G_u
+    ops.copy(u, buf.trial)
+    ops.axpby(nu, buf.d, 1.0, buf.trial)              # trial point u + nu d
+    F_trial = est(buf.trial, i, buf.G_trial)
+    ops.axpby(nu, buf.d, 0.0, buf.s)                  # s = nu d
+    ops.copy(buf.G_trial, buf.y)
+    ops.axpby(-1.0, buf.G_u, 1.0, buf.y)              # y = G_trial - G_u
+    hist.push(buf.s, buf.y)
+    hist.apply(buf.G_trial, buf.r, h0)
+    ops.axpby(-1.0, buf.r, 1.0, buf.d)                # d = d - H G_trial
+    ops.axpby(nu, buf.d, 1.0, u)
+    return min(F_u, F_trial)
+
+
+class IterateAverage:
+    """The returned estimate (App. D): the iterate itself until the energy
+    estimate first increases, then the w(i)-weighted mean of the iterates of
+    the following steps, accumulated on the device."""
+
+    def __init__(self, est: EncodedEstimator, weight: Callable[[int], float]):
+        self.ops = est.ops
+        self.weight = weight
+        self.on = False
+        self.total = self.ops.axpby(0.0, None, 0.0, est.empty())
+        self.wsum = 0.0
+        self.J_last = math.inf
+        self.estimate = est.empty()
+
+    def update(self, i: int, u: torch.Tensor, J: float) -> torch.Tensor:
+        if self.on:
+            wi = self.weight(i)
+            self.ops.axpby(wi, u, 1.0, self.total)
+            self.wsum += wi
+            self.ops.axpby(1.0 / self.wsum, self.total, 0.0, self.estimate)
+        else:
+            self.on = J > self.J_last
+            self.ops.copy(u, self.estimate)
+        self.J_last = J
+        return self.estimate
+
+
 def slbfgs(est: EncodedEstimator, u0: torch.Tensor, *, nu: float, n_evals: int, m_h: int = 64, h0: float = 1.0,
            u_min: float = -math.inf, u_max: float = math.inf, weight: Callable[[int], float] = lambda i: float(i) ** 3,
            callback: Optional[Callable] = None) -> Tuple[torch.Tensor, List[float]]:
-    """Algorithm 2 without line search.  Returns (u_hat, energy estimates J_i).
-    callback(i, u_hat, J_i) is called after every iteration."""
+    """Algorithm 2 without line search: quasi-Newton steps i = 1, 2, ... until
+    n_evals estimator calls (two per step) are spent, each followed by the
+    projection onto [u_min, u_max] and the iterate averaging.  Returns
+    (u_hat, energy estimates J_i); callback(i, u_hat, J_i) after every step."""
     ops = est.ops
-    n = u0.numel()
-    hist = LbfgsHistory(n, m_h, ops)
+    hist = LbfgsHistory(u0.numel(), m_h, ops)
     u = ops.copy(u0, est.empty())
-    z, t, s, y = est.empty(), est.empty(), est.empty(), est.empty()
-    G_u, G_z, r = est.empty(), est.empty(), est.empty()
-    u_bar = ops.axpby(0.0, None, 0.0, est.empty())
+    buf = _StepBuffers(est)
+    average = IterateAverage(est, weight)
     u_hat = ops.copy(u, est.empty())
-    w_bar = 0.0
-    J_prev = math.inf
-    averaging = False
-    n_evl = 0
-    i = 0
     Js: List[float] = []
+    i = 0
     try:
-        while n_evl < n_evals:
+        while 2 * i < n_evals:
             i += 1
-            F_u = est(u, i, G_u)
-            n_evl += 1
-            hist.apply(G_u, z, h0)
-            ops.axpby(0.0, None, -1.0, z)                 # z = -H G_u
-            ops.copy(u, t)
-            ops.axpby(nu, z, 1.0, t)                      # t = u + nu z
-            F_z = est(t, i, G_z)
-            n_evl += 1
-            ops.axpby(nu, z, 0.0, s)                      # s = nu z
-            ops.copy(G_z, y)
-            ops.axpby(-1.0, G_u, 1.0, y)                  # y = G_z - G_u
-            hist.push(s, y)
-            hist.apply(G_z, r, h0)
-            ops.axpby(-1.0, r, 1.0, z)                    # z = z - H G_z
-            ops.axpby(nu, z, 1.0, u)                      # u = u + nu z
+            J = quasi_newton_step(est, u, i, hist, nu, h0, buf)
             ops.clip(u, u_min, u_max)
-            J_i = min(F_u, F_z)
-            if averaging:
-                wi = weight(i)
-                ops.axpby(wi, u, 1.0, u_bar)
-                w_bar += wi
-                ops.axpby(1.0 / w_bar, u_bar, 0.0, u_hat)
-            else:
-                if J_i > J_prev:
-                    averaging = True
-                ops.copy(u, u_hat)
-            J_prev = J_i
-            Js.append(J_i)
+            u_hat = average.update(i, u, J)
+            Js.append(J)
             if callback is not None:
-                callback(i, u_hat, J_i)
+                callback(i, u_hat, J)
     finally:
         hist.close()
     return u_hat, Js

@@ -1,0 +1,139 @@
+"""GPU parity of the batched, served and full-size workloads at their own
+sizes, against stored FP64 oracle results (tests/golden/make_golden.py, which
+calls only oracle/ and synth/).
+
+* batched: 16 Rademacher-encoded TR gradients on 128^3 (600 steps, phantom
+  seeds 300..315, encoding seeds 1300..1315) in one batch-16 handle whose
+  time step is a replayed hipGraph: every gradient and misfit equals its
+  batch-1 solve bit for bit, and problems 0 and 1 match the oracle
+  (Sec. 3.2 encoding, App. B Alg. 1);
+* served: one forward and one gradient per multigrid level (96^3 @ 1 mm over
+  300 steps; 160^3 @ 0.75 mm and 224x224x112 @ 0.5 mm truncated to 150
+  steps) submitted together to the serving loop, against the oracle
+  (Sec. 3.3, App. C levels).
+Tolerances (FP32): traces rel l2 <= 1e-4, misfit and gradient on Gamma
+rel <= 1e-3.
+"""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden")
+sys.path.insert(0, GOLDEN)
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _golden(case):
+    return np.load(os.path.join(GOLDEN, f"{case}_oracle.npz"))
+
+
+def test_batch16_graph_equals_single_and_oracle():
+    from paper_2102_00755_amd import fwi
+    from synth import make_config
+    B = 16
+    probs = [make_config("batch", index=i) for i in range(B)]
+    base = probs[0]
+    print(f"batch B={B} shape={base.shape} nt={base.nt}", flush=True)
+    # one geometry for the batch: every emitter of the bowl is a source; the
+    # weights of problem i are its Rademacher weights on its encoded subset and
+    # zero elsewhere
+    emitters = base.meta["all_emitters"]
+    n_all = emitters.shape[0]
+    kw = fwi.problem_kwargs(base)
+    kw["src_ijk"] = emitters
+    W = np.zeros((B, n_all), dtype=np.int8)
+    for i, p in enumerate(probs):
+        assert np.array_equal(p.src_ijk, emitters[p.meta["emitter_index"]])
+        assert np.array_equal(p.gamma, base.gamma) and np.array_equal(p.rec_ijk, base.rec_ijk)
+        W[i, p.meta["emitter_index"]] = fwi.rademacher(p.enc_seed, p.n_src)
+    dev = torch.device("cuda", 0)
+    S = torch.from_numpy(np.repeat(base.pulse[:, None], n_all, axis=1).astype(np.float32)).to(dev)
+    S = S.unsqueeze(0).expand(B, -1, -1).contiguous()
+    Wt = torch.from_numpy(W).to(dev)
+    c_true = torch.stack([torch.from_numpy(p.c_true) for p in probs]).to(dev, torch.float32)
+    c_eval = torch.stack([torch.from_numpy(p.c_eval) for p in probs]).to(dev, torch.float32)
+    gold = {i: _golden(f"batch{i}") for i in (0, 1)}
+    side = torch.cuda.Stream(device=dev)      # step-graph capture needs a non-null stream
+    side.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(side):
+        _batch_and_single(B, kw, probs, base, W, S, Wt, c_true, c_eval, gold, dev)
+    side.synchronize()
+
+
+def _batch_and_single(B, kw, probs, base, W, S, Wt, c_true, c_eval, gold, dev):
+    from paper_2102_00755_amd import fwi
+    hb = fwi.Handle(**kw, batch=B)
+    hb.use_graph = True
+    traces = hb.forward(c_true, S, Wt).clone()
+    for i, ref in gold.items():
+        assert np.array_equal(ref["w"], W[i, probs[i].meta["emitter_index"]])
+        assert rel(traces[i].cpu().numpy(), ref["traces_true"]) < 1e-4, i
+    obs = traces.clone()
+    for i, ref in gold.items():       # the oracle's observed data where stored
+        obs[i] = torch.from_numpy(ref["traces_true"]).to(dev)
+    mis_b, g_b = hb.gradient(c_eval, S, Wt, obs)
+    mis_b, g_b = mis_b.clone(), g_b.clone()
+    hb.close()
+    g = base.gamma.astype(bool)
+    for i, ref in gold.items():
+        D = float(ref["misfit"])
+        assert abs(float(mis_b[i]) - D) <= 1e-3 * D, i
+        got = g_b[i].cpu().numpy()
+        assert rel(got[g], ref["grad_gamma"]) < 1e-3, i
+        assert np.all(got[~g] == 0)
+    h1 = fwi.Handle(**kw, batch=1)
+    h1.use_graph = True
+    for i in range(B):
+        m1, g1 = h1.gradient(c_eval[i], S[i], Wt[i], obs[i])
+        assert torch.equal(g1[0], g_b[i]), i
+        assert float(m1[0]) == float(mis_b[i]), i
+    h1.close()
+
+
+SERVE_CASES = ("serve96", "serve160", "serve224")
+
+
+def test_serving_levels_match_oracle():
+    import make_golden
+    from paper_2102_00755_amd import fwi
+    from paper_2102_00755_amd.serving import Level, Server
+    probs = {name: make_golden.problem(name) for name in SERVE_CASES}
+    gold = {name: _golden(name) for name in SERVE_CASES}
+    levels = [Level(name, fwi.problem_kwargs(p, precision=4)) for name, p in probs.items()]
+    budget = 3 * max(fwi.workspace_bytes(**dict(lv.kwargs), batch=4) for lv in levels)
+    srv = Server(levels, budget_bytes=budget, max_inflight=4)
+    futs = {}
+    for name, p in probs.items():
+        print(f"serving level {name} shape={p.shape} nt={p.nt}", flush=True)
+        ref = gold[name]
+        w = torch.from_numpy(fwi.rademacher(p.enc_seed, p.n_src))
+        assert np.array_equal(w.numpy(), ref["w"])
+        S = torch.from_numpy(p.src_signals().astype(np.float32))
+        c = torch.from_numpy(p.c_eval.astype(np.float32))
+        futs[name, "forward"] = srv.submit("forward", name, c, S, w)
+        futs[name, "gradient"] = srv.submit("gradient", name, c, S, w, torch.from_numpy(ref["obs"]))
+    results = {k: f.result(timeout=300) for k, f in futs.items()}
+    srv.close()
+    for name, p in probs.items():
+        ref = gold[name]
+        traces = results[name, "forward"][0].cpu().numpy()
+        assert rel(traces, ref["traces_eval"]) < 1e-4, name
+        mis, grad = results[name, "gradient"]
+        D = float(ref["misfit"])
+        assert abs(float(mis[0]) - D) <= 1e-3 * D, name
+        g = p.gamma.astype(bool)
+        got = grad[0].cpu().numpy()
+        assert rel(got[g], ref["grad_gamma"]) < 1e-3, name
+        assert np.all(got[~g] == 0), name
