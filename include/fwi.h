@@ -27,8 +27,10 @@
  *     abort crosses this boundary.  A handle is not thread-safe; distinct
  *     handles may be used concurrently (on distinct streams).
  *   - Supported sizes: nx even with nx/2 in, and ny, nz in, the set
- *     {8, 12, 16, 24, 32, 40, 48, 56, 64, 80, 96, 112, 128, 160, 224, 256, 448};
- *     other sizes return FWI_ERR_UNSUPPORTED.
+ *     {8, 12, 16, 24, 32, 40, 48, 56, 64, 80, 96, 112, 128, 160, 192, 224, 240,
+ *      256, 320, 384, 448, 480, 512} (2-, 3-, 5-, 7-smooth lengths; the paper's
+ *     PML-padded 480 x 480 x 256 grid among them); other sizes return
+ *     FWI_ERR_UNSUPPORTED.
  */
 #ifndef FWI_H_
 #define FWI_H_
@@ -184,15 +186,27 @@ int fwi_derivative(fwi_handle* h, const void* in, void* out, int32_t axis, int32
                    fwi_stream_t stream);
 
 /* Launch tuning of a handle: the row segment, in bytes, of the tiles of the
- * y passes, of the z pass of d- (Z1) and of the z pass of d+ (Z2); each 64 or
- * 128.  The tile width changes only which threads compute which columns, not
- * the arithmetic: results are bit-identical across tunings.  New handles
- * start from the build's defaults (measured fastest at 448x448x224);
+ * y passes, of the z pass of d- (Z1) and of the z pass of d+ (Z2), each 64 or
+ * 128; and the radix plan of the transforms of the y passes, of Z1, of Z2 and
+ * of the velocity and density x passes (length nx/2), each 0 or 1:
+ *   plan 0: the odd radices (7, 5, 3) first, then radix-8 stages with the
+ *           smaller power-of-two stage last (e.g. 224 = 7 * 8 * 4);
+ *   plan 1: the same radices with the power-of-two stages in reverse order
+ *           (224 = 7 * 4 * 8); lengths whose two plans coincide run plan 0.
+ * The tile width changes only which threads compute which columns, not the
+ * arithmetic: results are bit-identical across tile widths.  The two radix
+ * plans compute the same DFT in a different order of operations: results
+ * agree to rounding (both are parity-tested).  New handles start from the
+ * build's defaults (measured fastest at 448x448x224);
  * paper_2102_00755_amd.autotune measures the alternatives per grid. */
 typedef struct {
   int32_t y_tile_bytes;
   int32_t zm_tile_bytes;
   int32_t zp_tile_bytes;
+  int32_t y_plan;
+  int32_t zm_plan;
+  int32_t zp_plan;
+  int32_t x_plan;
 } fwi_tuning;
 
 /* Read the handle's tuning into *out. */

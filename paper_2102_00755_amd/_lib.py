@@ -32,7 +32,8 @@ FWI_MEAN = 32
 
 FWI_NOALLOC_MAX_PAIRS = 256   # static scratch of fwi_lbfgs_apply_noalloc
 
-SUPPORTED_LENGTHS = (8, 12, 16, 24, 32, 40, 48, 56, 64, 80, 96, 112, 128, 160, 224, 256, 448)
+SUPPORTED_LENGTHS = (8, 12, 16, 24, 32, 40, 48, 56, 64, 80, 96, 112, 128, 160, 192, 224, 240, 256, 320, 384, 448,
+                     480, 512)
 
 # every symbol declared in include/fwi.h
 EXPORTED = (
@@ -75,7 +76,8 @@ class FwiGeometry(ctypes.Structure):
 
 
 class FwiTuning(ctypes.Structure):
-    _fields_ = [("y_tile_bytes", c_int32), ("zm_tile_bytes", c_int32), ("zp_tile_bytes", c_int32)]
+    _fields_ = [("y_tile_bytes", c_int32), ("zm_tile_bytes", c_int32), ("zp_tile_bytes", c_int32),
+                ("y_plan", c_int32), ("zm_plan", c_int32), ("zp_plan", c_int32), ("x_plan", c_int32)]
 
 
 _lib = None

@@ -1,14 +1,23 @@
 """Autotuner of the launch tuning of a handle, with a persisted JSON cache.
 
-The tunable launch parameters are the row segments of the axis-pass tiles
-(64 or 128 bytes) of the three axis-pass kinds: y passes, the z pass of d-
-(Z1) and the z pass of d+ (Z2) (``fwi_set_tuning``).  Each kind runs as its
-own kernels, so each is tuned independently from the library's per-pass
-HIP-event timer: a short-horizon twin of the handle (same grid, geometry,
-precision and batch, ``steps`` time steps) runs a forward simulation with
-every tile width, timing every step, and per kind the width with the least
-time per launch wins.  Results are bit-identical across tunings, so the
-choice changes speed only.
+The tunable launch parameters (``fwi_set_tuning``) are the row segments of
+the axis-pass tiles (64 or 128 bytes) of the three axis-pass kinds — y
+passes, the z pass of d- (Z1) and the z pass of d+ (Z2) — and the radix plans
+of the transforms of the y passes, Z1, Z2 and the x passes (two orders of the
+same radices each).  A short-horizon
+twin of the handle (same grid, geometry, precision and batch, ``steps`` time
+steps) runs a forward simulation per candidate, timing every pass launch
+with the library's HIP-event timer:
+
+* tiles: each kind runs as its own kernels, so per kind the width with the
+  least time per launch wins;
+* radix plans (y passes, Z1, Z2, x passes): with the chosen tiles, by
+  coordinate descent on the total time per time step of all passes (a plan
+  changes a pass's compute and memory timing, which the neighbouring passes
+  feel): each kind's plan is switched to 1 if that lowers the total.
+
+Results are bit-identical across tile widths; the two radix plans agree to
+rounding.  The choice changes speed only.
 
 The cache maps a key (device name, precision, grid, batch) to the chosen
 tuning; it lives in ``$FWI_TUNING_CACHE`` or
@@ -114,14 +123,69 @@ def measure(handle: "fwi.Handle", steps: int = 24, repeats: int = 2) -> Dict[int
         twin.close()
 
 
+PLAN_FIELDS = ("y_plan", "zm_plan", "zp_plan", "x_plan")
+
+
+def step_ms(handle: "fwi.Handle", tunings, steps: int = 24, repeats: int = 2) -> list:
+    """Total ms per time step (all passes) of a forward simulation under each
+    tuning of `tunings`, on the same kind of twin as ``measure``."""
+    kw = dict(handle.kwargs)
+    kw["nt"] = int(steps)
+    twin = fwi.Handle(**kw, batch=handle.batch, device=handle.device.index or 0)
+    try:
+        dev, dt = twin.device, twin.dtype
+        c0 = 0.5 * (float(kw["c_min"]) + float(kw["c_max"]))
+        c = torch.full((twin.batch,) + twin.shape, c0, device=dev, dtype=dt)
+        src = torch.zeros((twin.batch, twin.nt, twin.n_src), device=dev, dtype=dt)
+        w = torch.ones((twin.batch, twin.n_src), device=dev, dtype=torch.int8)
+        out = []
+        for tuning in tunings:
+            twin.tuning = tuning
+            twin.forward(c, src, w)                       # warm-up
+            torch.cuda.synchronize(dev)
+            best = float("inf")
+            for _ in range(repeats):
+                twin.timing_enable(1)
+                twin.timing_read()
+                twin.forward(c, src, w)
+                torch.cuda.synchronize(dev)
+                twin.timing_enable(0)
+                tim = twin.timing_read()
+                best = min(best, sum(ms for (_, ms, _) in tim.values()) / twin.nt)
+            out.append(best)
+        return out
+    finally:
+        twin.close()
+
+
+def choose_plans(handle: "fwi.Handle", tiles: dict, steps: int = 24, step_fn: Optional[Callable] = None):
+    """Radix plans by coordinate descent on the total step time: starting from
+    plan 0 everywhere, each pass kind's plan is switched to 1 if that lowers
+    the time.  Returns (plans, [(tuning, ms per step), ...])."""
+    fn = step_fn or step_ms
+    cur = dict(tiles, **{f: 0 for f in PLAN_FIELDS})
+    best = fn(handle, [cur], steps)[0]
+    log = [(dict(cur), best)]
+    for f in PLAN_FIELDS:
+        trial = dict(cur, **{f: 1})
+        t = fn(handle, [trial], steps)[0]
+        log.append((dict(trial), t))
+        if t < best:
+            cur, best = trial, t
+    return {f: int(cur[f]) for f in PLAN_FIELDS}, log
+
+
 def tune(handle: "fwi.Handle", steps: int = 24, cache: Optional[str] = None,
-         measure_fn: Optional[Callable] = None) -> dict:
+         measure_fn: Optional[Callable] = None, step_fn: Optional[Callable] = None) -> dict:
     """Measure, choose, store in the cache and apply; returns the tuning."""
     per_width = (measure_fn or measure)(handle, steps)
     choice = choose(per_width)
+    plans, log = choose_plans(handle, choice, steps, step_fn)
+    choice.update(plans)
     key = cache_key(torch.cuda.get_device_name(handle.device), handle.precision, handle.shape, handle.batch)
     data = load_cache(cache)
-    data[key] = dict(choice, measured_ms_per_launch={str(k): v for k, v in per_width.items()}, steps=int(steps))
+    data[key] = dict(choice, measured_ms_per_launch={str(k): v for k, v in per_width.items()},
+                     measured_ms_per_step_by_plans=[[t, ms] for t, ms in log], steps=int(steps))
     save_cache(data, cache)
     handle.tuning = choice
     return choice
@@ -131,8 +195,8 @@ def apply(handle: "fwi.Handle", cache: Optional[str] = None, steps: int = 24) ->
     """Apply the cached tuning of the handle's key, measuring it on a miss."""
     key = cache_key(torch.cuda.get_device_name(handle.device), handle.precision, handle.shape, handle.batch)
     entry = load_cache(cache).get(key)
-    if entry is not None:
-        choice = {f: int(entry[f]) for f in KIND_PASSES}
+    if entry is not None and all(f in entry for f in PLAN_FIELDS):
+        choice = {f: int(entry[f]) for f in tuple(KIND_PASSES) + PLAN_FIELDS}
         handle.tuning = choice
         return choice
     return tune(handle, steps=steps, cache=cache)

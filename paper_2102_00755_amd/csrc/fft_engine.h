@@ -29,19 +29,42 @@ struct RadixPlan {
   int r[8];
 };
 
-constexpr RadixPlan make_plan(int L) {
+// Radix plan of length L.  Plan 0: the odd radices (7, 5, 3) first, then
+// the power-of-two part as radix-8 stages with one radix-4 or radix-2 stage
+// (two radix-4 stages for 16) last.  Plan 1: the same radices with the
+// power-of-two stages in reverse order (e.g. 224 = 7 * 8 * 4 -> 7 * 4 * 8).
+// Both compute the same DFT; they differ in rounding, in the thread mapping
+// of each stage and in the twiddle pattern, and so in speed (a run-time
+// choice of the x passes: fwi_set_tuning).
+constexpr RadixPlan make_plan(int L, int PL = 0) {
   RadixPlan p{0, {0, 0, 0, 0, 0, 0, 0, 0}};
   int m = L;
   while (m % 7 == 0) { p.r[p.n++] = 7; m /= 7; }
   while (m % 5 == 0) { p.r[p.n++] = 5; m /= 5; }
   while (m % 3 == 0) { p.r[p.n++] = 3; m /= 3; }
+  const int first2 = p.n;
   while (m > 1) {
     if (m == 16) { p.r[p.n++] = 4; p.r[p.n++] = 4; m = 1; }
     else if (m % 8 == 0) { p.r[p.n++] = 8; m /= 8; }
     else if (m % 4 == 0) { p.r[p.n++] = 4; m /= 4; }
     else { p.r[p.n++] = 2; m /= 2; }
   }
+  if (PL == 1) {
+    for (int i = first2, j = p.n - 1; i < j; ++i, --j) {
+      const int t = p.r[i];
+      p.r[i] = p.r[j];
+      p.r[j] = t;
+    }
+  }
   return p;
+}
+
+// Plan 1 differs from plan 0 (otherwise only plan 0 is instantiated)
+constexpr bool plan_differs(int L) {
+  const RadixPlan a = make_plan(L, 0), b = make_plan(L, 1);
+  for (int i = 0; i < a.n; ++i)
+    if (a.r[i] != b.r[i]) return true;
+  return false;
 }
 
 constexpr bool plan_ok(int L) {
@@ -53,8 +76,8 @@ constexpr bool plan_ok(int L) {
   return m == 1 && L >= 2;
 }
 
-constexpr int plan_prefix(int L, int s) {
-  RadixPlan p = make_plan(L);
+constexpr int plan_prefix(int L, int s, int PL = 0) {
+  RadixPlan p = make_plan(L, PL);
   int ns = 1;
   for (int i = 0; i < s; ++i) ns *= p.r[i];
   return ns;
@@ -205,14 +228,14 @@ template <int TW, int NS, int K, int NT> struct StageMap {
   static constexpr int NK = A ? K / KB : K;                      // k values per thread
 };
 
-template <typename T, int L, int TW, int TWP, int NT, bool INV, int S>
+template <typename T, int L, int TW, int TWP, int NT, bool INV, int S, int PL>
 struct Stage {
   static __device__ __forceinline__ void run(cplx<T>* buf, const cplx<T>* __restrict__ tw) {
-    constexpr RadixPlan P = make_plan(L);
+    constexpr RadixPlan P = make_plan(L, PL);
     if constexpr (S < P.n) {
       using C = cplx<T>;
       constexpr int R = P.r[S];
-      constexpr int NS = plan_prefix(L, S);
+      constexpr int NS = plan_prefix(L, S, PL);
       constexpr int LR = L / R;
       constexpr int K = L / (NS * R);
       constexpr int TSTEP = L / (NS * R);
@@ -264,7 +287,7 @@ struct Stage {
         }
       }
       __syncthreads();
-      Stage<T, L, TW, TWP, NT, INV, S + 1>::run(buf, tw);
+      Stage<T, L, TW, TWP, NT, INV, S + 1, PL>::run(buf, tw);
     }
   }
 };
@@ -272,10 +295,10 @@ struct Stage {
 // In-place length-L FFT of TW columns in LDS.  Must be called by all NT
 // threads of the workgroup; begins and ends with the LDS contents valid for
 // every thread (the caller synchronises before the call).
-template <typename T, int L, int TW, int TWP, int NT, bool INV>
+template <typename T, int L, int TW, int TWP, int NT, bool INV, int PL = 0>
 __device__ __forceinline__ void lds_fft(cplx<T>* buf, const cplx<T>* __restrict__ tw) {
   static_assert(plan_ok(L), "FFT length must factor into 2, 3, 5, 7");
-  Stage<T, L, TW, TWP, NT, INV, 0>::run(buf, tw);
+  Stage<T, L, TW, TWP, NT, INV, 0, PL>::run(buf, tw);
 }
 
 }  // namespace fwi

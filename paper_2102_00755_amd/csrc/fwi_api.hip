@@ -323,6 +323,10 @@ struct EngineBase {
   PassTimer timer;
   // axis-pass tile row segments in bytes (run-time tuning, fwi_set_tuning)
   int tile_bytes[3] = {FWI_Y_TILE_BYTES, FWI_ZM_TILE_BYTES, FWI_ZP_TILE_BYTES};
+  // radix plans of the axis-pass kinds (AxisKind) and of the velocity and
+  // density x passes (run-time tuning)
+  int plans[3] = {FWI_Y_PLAN, FWI_ZM_PLAN, FWI_ZP_PLAN};
+  int x_plan = FWI_X_PLAN;
 };
 
 template <typename T> struct Engine : EngineBase {
@@ -575,33 +579,33 @@ template <typename T> struct Engine : EngineBase {
     const double S = sbytes(), F = fbytes(), ns = nslots;
     hipEvent_t ev;
     ev = timer.begin(st);
-    FWI_HIP(launch_axis_y<T>(d.ny, false, ty, gy, st, axis_args(slot0, na, slot1, 1, 0)));   // Y3
+    FWI_HIP(launch_axis_y<T>(d.ny, false, ty, plans[AK_Y], gy, st, axis_args(slot0, na, slot1, 1, 0)));   // Y3
     timer.end(ev, FWI_PASS_Y_FWD, 2 * ns * S, st);
     ev = timer.begin(st);
-    FWI_HIP(launch_axis_zp<T>(d.nz, tzp, gz, st, axis_args(slot0, na, slot1, 1, 0)));        // Z2
+    FWI_HIP(launch_axis_zp<T>(d.nz, tzp, plans[AK_ZPLUS], gz, st, axis_args(slot0, na, slot1, 1, 0)));        // Z2
     timer.end(ev, FWI_PASS_Z_PLUS, 3 * ns * S, st);
     ev = timer.begin(st);
-    FWI_HIP(launch_axis_yv<T>(d.ny, 0, tyv, gyv, st, axis_args(slot0, na, slot1, 1, 0)));    // Y4: Q, v_y
+    FWI_HIP(launch_axis_yv<T>(d.ny, 0, tyv, plans[AK_Y], gyv, st, axis_args(slot0, na, slot1, 1, 0)));    // Y4: Q, v_y
     timer.end(ev, FWI_PASS_Y_VEL_Q, 5 * ns * S, st);
     ev = timer.begin(st);
-    FWI_HIP(launch_axis_yv<T>(d.ny, 1, tyv, gyv, st, axis_args(slot0, na, slot1, 1, 0)));    // Y4: R, v_z
+    FWI_HIP(launch_axis_yv<T>(d.ny, 1, tyv, plans[AK_Y], gyv, st, axis_args(slot0, na, slot1, 1, 0)));    // Y4: R, v_z
     timer.end(ev, FWI_PASS_Y_VEL_R, 4 * ns * S, st);
     XArgs<T> xa;
     xa.slots = slot_table; xa.slot0 = slot0; xa.na = na; xa.slot1 = slot1;
     xa.d = d; xa.tb = tb; xa.dt_rho = (T)(p.dt / p.rho0);
     const int lpb = x_lines_per_block_vel<T>(d.M);
     ev = timer.begin(st);
-    FWI_HIP(launch_x_vel<T>(d.M, dim3((d.nlines + lpb - 1) / lpb, nslots), st, xa));       // X1 (v_x)
+    FWI_HIP(launch_x_vel<T>(d.M, x_plan, dim3((d.nlines + lpb - 1) / lpb, nslots), st, xa));   // X1 (v_x)
     timer.end(ev, FWI_PASS_X_VEL, ns * (2 * S + 2 * F), st);
     if (half_only) return FWI_OK;
     ev = timer.begin(st);
-    FWI_HIP(launch_axis_y<T>(d.ny, false, ty, gy, st, axis_args(slot0, na, slot1, 1, 0)));   // Y1 (v_x)
+    FWI_HIP(launch_axis_y<T>(d.ny, false, ty, plans[AK_Y], gy, st, axis_args(slot0, na, slot1, 1, 0)));   // Y1 (v_x)
     timer.end(ev, FWI_PASS_Y_FWD, 2 * ns * S, st);
     ev = timer.begin(st);
-    FWI_HIP(launch_axis_zm<T>(d.nz, tzm, gz3, st, axis_args(slot0, na, slot1, 3, 0)));       // Z1
+    FWI_HIP(launch_axis_zm<T>(d.nz, tzm, plans[AK_ZMINUS], gz3, st, axis_args(slot0, na, slot1, 3, 0)));       // Z1
     timer.end(ev, FWI_PASS_Z_MINUS, 6 * ns * S, st);
     ev = timer.begin(st);
-    FWI_HIP(launch_axis_y<T>(d.ny, true, ty, gy3, st, axis_args(slot0, na, slot1, 3, 0)));   // Y2
+    FWI_HIP(launch_axis_y<T>(d.ny, true, ty, plans[AK_Y], gy3, st, axis_args(slot0, na, slot1, 3, 0)));   // Y2
     timer.end(ev, FWI_PASS_Y_INV, 6 * ns * S, st);
     return FWI_OK;
   }
@@ -621,7 +625,7 @@ template <typename T> struct Engine : EngineBase {
     const int lpb = x_lines_per_block_den<T>(d.M);
     const double S = sbytes(), F = fbytes(), t = sizeof(T);
     hipEvent_t ev = (mode == XM_FWD || mode == XM_PAIR) ? timer.begin(st) : nullptr;
-    FWI_HIP(launch_x_den<T>(d.M, mode, dim3((d.nlines + lpb - 1) / lpb, B), st, a));
+    FWI_HIP(launch_x_den<T>(d.M, mode, x_plan, dim3((d.nlines + lpb - 1) / lpb, B), st, a));
     if (mode == XM_FWD) {
       // 3 spectra in, 1 out, split densities r/w, c0, source row, trace row, tape row
       const double b = B * (4 * S + 7 * F + t * (d.n_src + d.n_rec + (a.tape ? d.n_bnd : 0)));
@@ -658,9 +662,9 @@ template <typename T> struct Engine : EngineBase {
     const int ns = (k1 < 0) ? B : 2 * B;
     const int ty = tile_bytes[AK_Y], tz = tile_bytes[AK_ZMINUS];
     const AxisArgs<T> ax = axis_args(s0, B, s1, 2, 0);
-    FWI_HIP(launch_axis_y<T>(d.ny, false, ty, dim3(ntx(AK_Y) * d.nz, ns * 2), st, ax));
-    FWI_HIP(launch_axis_zf<T>(d.nz, tz, dim3(ntx(AK_ZMINUS) * d.ny, ns * 2), st, ax));
-    FWI_HIP(launch_axis_y<T>(d.ny, true, ty, dim3(ntx(AK_Y) * d.nz, ns * 2), st, ax));
+    FWI_HIP(launch_axis_y<T>(d.ny, false, ty, plans[AK_Y], dim3(ntx(AK_Y) * d.nz, ns * 2), st, ax));
+    FWI_HIP(launch_axis_zf<T>(d.nz, tz, plans[AK_ZMINUS], dim3(ntx(AK_ZMINUS) * d.ny, ns * 2), st, ax));
+    FWI_HIP(launch_axis_y<T>(d.ny, true, ty, plans[AK_Y], dim3(ntx(AK_Y) * d.nz, ns * 2), st, ax));
     const int lpe = x_lines_per_block_eos<T>(d.M);
     const dim3 ge((d.nlines + lpe - 1) / lpe, B);
     FWI_HIP(launch_x_lossy<T>(d.M, 1, k0, ge, st, a));
@@ -1095,12 +1099,12 @@ template <typename T> struct Engine : EngineBase {
     if (forward) {
       if (!in) return fail(FWI_ERR_INVALID_ARG, "NULL field");
       FWI_HIP(launch_x_r2c<T>(d.M, gx, st, xa, (const T*)in, 0));
-      FWI_HIP(launch_axis_y<T>(d.ny, false, ty, dim3(ntx(AK_Y) * d.nz, 1), st, axis_args(s, 1, s, 1, 0)));
-      FWI_HIP(launch_axis_z<T>(d.nz, false, tz, dim3(ntx(AK_ZMINUS) * d.ny, 1), st, axis_args(s, 1, s, 1, 0)));
+      FWI_HIP(launch_axis_y<T>(d.ny, false, ty, plans[AK_Y], dim3(ntx(AK_Y) * d.nz, 1), st, axis_args(s, 1, s, 1, 0)));
+      FWI_HIP(launch_axis_z<T>(d.nz, false, tz, plans[AK_ZMINUS], dim3(ntx(AK_ZMINUS) * d.ny, 1), st, axis_args(s, 1, s, 1, 0)));
     } else {
       if (!out) return fail(FWI_ERR_INVALID_ARG, "NULL field");
-      FWI_HIP(launch_axis_z<T>(d.nz, true, tz, dim3(ntx(AK_ZMINUS) * d.ny, 1), st, axis_args(s, 1, s, 1, 0)));
-      FWI_HIP(launch_axis_y<T>(d.ny, true, ty, dim3(ntx(AK_Y) * d.nz, 1), st, axis_args(s, 1, s, 1, 0)));
+      FWI_HIP(launch_axis_z<T>(d.nz, true, tz, plans[AK_ZMINUS], dim3(ntx(AK_ZMINUS) * d.ny, 1), st, axis_args(s, 1, s, 1, 0)));
+      FWI_HIP(launch_axis_y<T>(d.ny, true, ty, plans[AK_Y], dim3(ntx(AK_Y) * d.nz, 1), st, axis_args(s, 1, s, 1, 0)));
       FWI_HIP(launch_x_c2r<T>(d.M, gx, st, xa, (T*)out, 0, nullptr));
     }
     return FWI_OK;
@@ -1124,15 +1128,15 @@ template <typename T> struct Engine : EngineBase {
     const int f = sign > 0 ? 0 : axis;
     FWI_HIP(launch_x_r2c<T>(d.M, gx, st, xa, (const T*)in, f));
     const int ty = tile_bytes[AK_Y], tzm = tile_bytes[AK_ZMINUS], tzp = tile_bytes[AK_ZPLUS];
-    FWI_HIP(launch_axis_y<T>(d.ny, false, ty, dim3(ntx(AK_Y) * d.nz, 1), st, axis_args(s, 1, s, 1, f)));
+    FWI_HIP(launch_axis_y<T>(d.ny, false, ty, plans[AK_Y], dim3(ntx(AK_Y) * d.nz, 1), st, axis_args(s, 1, s, 1, f)));
     if (sign > 0) {
       // Z2 and the split inverse y pass of the time step; the x shift factor
       // of d+_x is applied by the C2R
-      FWI_HIP(launch_axis_zp<T>(d.nz, tzp, dim3(ntx(AK_ZPLUS) * d.ny, 1), st, axis_args(s, 1, s, 1, 0)));
-      FWI_HIP(launch_axis_ys<T>(d.ny, ty, dim3(ntx(AK_Y) * d.nz, 2), st, axis_args(s, 1, s, 2, 0)));
+      FWI_HIP(launch_axis_zp<T>(d.nz, tzp, plans[AK_ZPLUS], dim3(ntx(AK_ZPLUS) * d.ny, 1), st, axis_args(s, 1, s, 1, 0)));
+      FWI_HIP(launch_axis_ys<T>(d.ny, ty, plans[AK_Y], dim3(ntx(AK_Y) * d.nz, 2), st, axis_args(s, 1, s, 2, 0)));
     } else {
-      FWI_HIP(launch_axis_zm<T>(d.nz, tzm, dim3(ntx(AK_ZMINUS) * d.ny, 1), st, axis_args(s, 1, s, 1, axis)));
-      FWI_HIP(launch_axis_y<T>(d.ny, true, ty, dim3(ntx(AK_Y) * d.nz, 1), st, axis_args(s, 1, s, 1, axis)));
+      FWI_HIP(launch_axis_zm<T>(d.nz, tzm, plans[AK_ZMINUS], dim3(ntx(AK_ZMINUS) * d.ny, 1), st, axis_args(s, 1, s, 1, axis)));
+      FWI_HIP(launch_axis_y<T>(d.ny, true, ty, plans[AK_Y], dim3(ntx(AK_Y) * d.nz, 1), st, axis_args(s, 1, s, 1, axis)));
     }
     FWI_HIP(launch_x_c2r<T>(d.M, gx, st, xa, (T*)out, axis, (sign > 0 && axis == 0) ? tb.sfac_p[0] : nullptr));
     return FWI_OK;
@@ -1375,6 +1379,10 @@ int fwi_get_tuning(const fwi_handle* h, fwi_tuning* out) {
   out->y_tile_bytes = h->eng->tile_bytes[AK_Y];
   out->zm_tile_bytes = h->eng->tile_bytes[AK_ZMINUS];
   out->zp_tile_bytes = h->eng->tile_bytes[AK_ZPLUS];
+  out->y_plan = h->eng->plans[AK_Y];
+  out->zm_plan = h->eng->plans[AK_ZMINUS];
+  out->zp_plan = h->eng->plans[AK_ZPLUS];
+  out->x_plan = h->eng->x_plan;
   return FWI_OK;
 }
 
@@ -1383,7 +1391,14 @@ int fwi_set_tuning(fwi_handle* h, const fwi_tuning* t) {
   const int v[3] = {t->y_tile_bytes, t->zm_tile_bytes, t->zp_tile_bytes};
   for (int k = 0; k < 3; ++k)
     if (v[k] != 64 && v[k] != 128) return fail(FWI_ERR_INVALID_ARG, "tile bytes must be 64 or 128");
-  for (int k = 0; k < 3; ++k) h->eng->tile_bytes[k] = v[k];
+  const int pl[4] = {t->y_plan, t->zm_plan, t->zp_plan, t->x_plan};
+  for (int k = 0; k < 4; ++k)
+    if (pl[k] != 0 && pl[k] != 1) return fail(FWI_ERR_INVALID_ARG, "radix plans must be 0 or 1");
+  for (int k = 0; k < 3; ++k) {
+    h->eng->tile_bytes[k] = v[k];
+    h->eng->plans[k] = pl[k];
+  }
+  h->eng->x_plan = pl[3];
   return FWI_OK;
 }
 

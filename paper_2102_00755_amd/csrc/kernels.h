@@ -74,6 +74,27 @@ namespace fwi {
 #ifndef FWI_YV_TILE_BYTES
 #define FWI_YV_TILE_BYTES 0
 #endif
+// FWI_Y_PLAN, FWI_ZM_PLAN, FWI_ZP_PLAN, FWI_X_PLAN
+//                      default radix plans (make_plan: 0 or 1) of the y passes,
+//                      Z1, Z2 and the velocity / density x passes.  At
+//                      448x448x224 FP32 (same box, alternating runs) plan 1 of
+//                      Z2 (224 = 7*4*8) gives 25 410 Mcell-steps/s against
+//                      25 190 with plan 0: Z2 itself is 3 % slower, but its
+//                      stores leave the caches in a state the following inverse
+//                      y passes and X1 read 2-3 % faster; the other kinds'
+//                      plans change the total by less than 0.1 %.
+#ifndef FWI_Y_PLAN
+#define FWI_Y_PLAN 0
+#endif
+#ifndef FWI_ZM_PLAN
+#define FWI_ZM_PLAN 0
+#endif
+#ifndef FWI_ZP_PLAN
+#define FWI_ZP_PLAN 1
+#endif
+#ifndef FWI_X_PLAN
+#define FWI_X_PLAN 0
+#endif
 #ifndef FWI_Z_MIN_WAVES
 #define FWI_Z_MIN_WAVES 0
 #endif
@@ -242,7 +263,7 @@ template <int TBYTES> __device__ __forceinline__ int tile_linear() {
 }
 
 // Y pass: in-place FFT along y of nf fields per slot.  L == ny.
-template <typename T, int L, bool INV, int TB>
+template <typename T, int L, bool INV, int TB, int PL = 0>
 __global__ void __launch_bounds__(axis_nt(L, tile_tw<T, TB>()))
 k_axis_y(AxisArgs<T> a) {
   using C = cplx<T>;
@@ -261,13 +282,13 @@ k_axis_y(AxisArgs<T> a) {
   const int ncol = min(TW, (int)px - tile * TW);
   tile_load<T, L, TW, NT>(buf, g, px, ncol, twl, a.tb.tw_y);
   __syncthreads();
-  lds_fft<T, L, TW, TW, NT, INV>(buf, twl);
+  lds_fft<T, L, TW, TW, NT, INV, PL>(buf, twl);
   tile_store<T, L, TW, NT>(buf, g, px, ncol);
 }
 
 // Plain z pass: in-place FFT along z of nf fields per slot (grid transfers of
 // the coarse-to-fine scheme).  L == nz.
-template <typename T, int L, bool INV, int TB>
+template <typename T, int L, bool INV, int TB, int PL = 0>
 __global__ void __launch_bounds__(axis_nt(L, tile_tw<T, TB>()))
 k_axis_z(AxisArgs<T> a) {
   using C = cplx<T>;
@@ -287,7 +308,7 @@ k_axis_z(AxisArgs<T> a) {
   const int ncol = min(TW, (int)px - tile * TW);
   tile_load<T, L, TW, NT>(buf, g, rstride, ncol, twl, a.tb.tw_z);
   __syncthreads();
-  lds_fft<T, L, TW, TW, NT, INV>(buf, twl);
+  lds_fft<T, L, TW, TW, NT, INV, PL>(buf, twl);
   tile_store<T, L, TW, NT>(buf, g, rstride, ncol);
 }
 
@@ -337,7 +358,7 @@ __device__ __forceinline__ void z_apply(cplx<T>* buf, const cplx<T>* m, const cp
 
 // Z pass of the velocity divergence terms: field f -> F_z^-1 m-_f F_z field f
 // (eq. DisPartDevSt with the minus shift).  L == nz.
-template <typename T, int L, int TB>
+template <typename T, int L, int TB, int PL = 0>
 __global__ void __launch_bounds__(axis_nt(L, tile_tw<T, TB>())) FWI_Z_WAVES_ATTR
 k_axis_z_minus(AxisArgs<T> a) {
   using C = cplx<T>;
@@ -363,10 +384,10 @@ k_axis_z_minus(AxisArgs<T> a) {
   z_mult<T, L, TW, NT>(a, a.tb.sfac_m, f, kx, y, kap, m);
   tile_load<T, L, TW, NT>(buf, g, rstride, ncol, twl, a.tb.tw_z);
   __syncthreads();
-  lds_fft<T, L, TW, TW, NT, false>(buf, twl);
+  lds_fft<T, L, TW, TW, NT, false, PL>(buf, twl);
   z_apply<T, L, TW, NT>(buf, m, nullptr);
   __syncthreads();
-  lds_fft<T, L, TW, TW, NT, true>(buf, twl);
+  lds_fft<T, L, TW, TW, NT, true, PL>(buf, twl);
   tile_store<T, L, TW, NT>(buf, g, rstride, ncol);
 }
 
@@ -377,7 +398,7 @@ k_axis_z_minus(AxisArgs<T> a) {
 // applied later, in the y pass (y) and the x pass (x), where those wave
 // numbers are at hand: one spectrum less is written here and read there.
 // L == nz.
-template <typename T, int L, int TB>
+template <typename T, int L, int TB, int PL = 0>
 __global__ void __launch_bounds__(axis_nt(L, tile_tw<T, TB>())) FWI_Z_WAVES_ATTR
 k_axis_z_plus(AxisArgs<T> a) {
   using C = cplx<T>;
@@ -404,7 +425,7 @@ k_axis_z_plus(AxisArgs<T> a) {
   z_mult<T, L, TW, NT>(a, a.tb.sfac_p, 2, kx, y, kap, m);
   tile_load<T, L, TW, NT>(buf, s0 + off, rstride, ncol, twl, a.tb.tw_z);
   __syncthreads();
-  lds_fft<T, L, TW, TW, NT, false>(buf, twl);
+  lds_fft<T, L, TW, TW, NT, false, PL>(buf, twl);
   C xr[EPT];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
@@ -418,12 +439,12 @@ k_axis_z_plus(AxisArgs<T> a) {
     if ((L * TW) % NT == 0 || e < L * TW) buf[e] = cscale(xr[i], kap[i]);
   }
   __syncthreads();
-  lds_fft<T, L, TW, TW, NT, true>(buf, twl);
+  lds_fft<T, L, TW, TW, NT, true, PL>(buf, twl);
   tile_store<T, L, TW, NT>(buf, s0 + off, rstride, ncol);
   __syncthreads();
   z_apply<T, L, TW, NT>(buf, m, xr);
   __syncthreads();
-  lds_fft<T, L, TW, TW, NT, true>(buf, twl);
+  lds_fft<T, L, TW, TW, NT, true, PL>(buf, twl);
   tile_store<T, L, TW, NT>(buf, s2 + off, rstride, ncol);
 }
 
@@ -441,7 +462,7 @@ __device__ __forceinline__ double real_pow(double x, double e) { return pow(x, e
 // m_f = |k|^{2 e_f} / (nx ny nz), |k|^2 = kx^2 + ky^2 + kz^2, and m_f = 0 at
 // k = 0: e_0 = (y - 1) / 2 for s (field 0), e_1 = (y - 2) / 2 for d (field 1).
 // L == nz.
-template <typename T, int L, int TB>
+template <typename T, int L, int TB, int PL = 0>
 __global__ void __launch_bounds__(axis_nt(L, tile_tw<T, TB>()))
 k_axis_z_frac(AxisArgs<T> a) {
   using C = cplx<T>;
@@ -480,21 +501,21 @@ k_axis_z_frac(AxisArgs<T> a) {
   tile_commit<T, L, TW, NT>(buf, tmp);
   tw_commit<T, L, NT>(twl, tt);
   __syncthreads();
-  lds_fft<T, L, TW, TW, NT, false>(buf, twl);
+  lds_fft<T, L, TW, TW, NT, false, PL>(buf, twl);
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int e = (int)threadIdx.x + i * NT;
     if ((L * TW) % NT == 0 || e < L * TW) buf[e] = cscale(buf[e], m[i]);
   }
   __syncthreads();
-  lds_fft<T, L, TW, TW, NT, true>(buf, twl);
+  lds_fft<T, L, TW, TW, NT, true, PL>(buf, twl);
   tile_store<T, L, TW, NT>(buf, g, rstride, ncol);
 }
 
 // Inverse y pass after Z2: per slot, part 0 reads Q (field 0) and writes
 // F_y^-1 Q to field 0 and F_y^-1 (i k_y e^{+i k_y dy/2} Q) to field 1; part 1
 // transforms R (field 2) in place.  grid.y = 2 x slots.  L == ny.
-template <typename T, int L, int TB>
+template <typename T, int L, int TB, int PL = 0>
 __global__ void __launch_bounds__(axis_nt(L, tile_tw<T, TB>()))
 k_axis_y_split(AxisArgs<T> a) {
   using C = cplx<T>;
@@ -523,7 +544,7 @@ k_axis_y_split(AxisArgs<T> a) {
   tw_commit<T, L, NT>(twl, tt);
   if (part == 0) tw_commit<T, L, NT>(sfl, ts);
   __syncthreads();
-  lds_fft<T, L, TW, TW, NT, true>(buf, twl);
+  lds_fft<T, L, TW, TW, NT, true, PL>(buf, twl);
   tile_store<T, L, TW, NT>(buf, g, px, ncol);
   if (part == 0) {
     __syncthreads();
@@ -533,7 +554,7 @@ k_axis_y_split(AxisArgs<T> a) {
       if (E % NT == 0 || e < E) buf[e] = cmul(sfl[e / TW], tmp[i]);
     }
     __syncthreads();
-    lds_fft<T, L, TW, TW, NT, true>(buf, twl);
+    lds_fft<T, L, TW, TW, NT, true, PL>(buf, twl);
     tile_store<T, L, TW, NT>(buf, a.slots[s].spec[1] + off, px, ncol);
   }
 }
@@ -553,14 +574,14 @@ k_axis_y_split(AxisArgs<T> a) {
 //           V_z <- L_z (L_z V_z - nx dt/rho0 G);  F_y V_z -> field 2
 // The two parts are separate kernels so that each gets its own register
 // allocation.  L == ny.
-template <typename T, int L, int TW, int NT>
+template <typename T, int L, int TW, int NT, int PL>
 __device__ __forceinline__ void y_vel_update(cplx<T>* buf, const cplx<T>* twl, const cplx<T>* vs,
                                              const T* lam_row, T lam_all, T vcoef, cplx<T>* gv, cplx<T>* gout,
                                              size_t px, int ncol) {
   using C = cplx<T>;
   constexpr int E = L * TW;
   constexpr int EPT = (E + NT - 1) / NT;
-  lds_fft<T, L, TW, TW, NT, true>(buf, twl);
+  lds_fft<T, L, TW, TW, NT, true, PL>(buf, twl);
   // each thread updates the elements it loaded (same element map as the tile load)
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
@@ -574,11 +595,11 @@ __device__ __forceinline__ void y_vel_update(cplx<T>* buf, const cplx<T>* twl, c
     }
   }
   __syncthreads();
-  lds_fft<T, L, TW, TW, NT, false>(buf, twl);
+  lds_fft<T, L, TW, TW, NT, false, PL>(buf, twl);
   tile_store<T, L, TW, NT>(buf, gout, px, ncol);
 }
 
-template <typename T, int L, int TB, int PART>
+template <typename T, int L, int TB, int PART, int PL = 0>
 __global__ void __launch_bounds__(axis_nt(L, tile_tw<T, TB>()))
 k_axis_y_vel(AxisArgs<T> a) {
   using C = cplx<T>;
@@ -620,7 +641,7 @@ k_axis_y_vel(AxisArgs<T> a) {
       }
     }
     __syncthreads();
-    lds_fft<T, L, TW, TW, NT, true>(buf, twl);
+    lds_fft<T, L, TW, TW, NT, true, PL>(buf, twl);
     tile_store<T, L, TW, NT>(buf, gq, px, ncol);     // F_y^-1 Q
     __syncthreads();
 #pragma unroll
@@ -632,7 +653,7 @@ k_axis_y_vel(AxisArgs<T> a) {
     C* const gv = reinterpret_cast<C*>(sl.v[1]) + off;
     tile_prefetch<T, L, TW, NT>(vs, gv, px, ncol);     // in flight during the next transform
     __syncthreads();
-    y_vel_update<T, L, TW, NT>(buf, twl, vs, lml, (T)1, a.vcoef, gv, sl.spec[1] + off, px, ncol);
+    y_vel_update<T, L, TW, NT, PL>(buf, twl, vs, lml, (T)1, a.vcoef, gv, sl.spec[1] + off, px, ncol);
   } else {
     C* const gr = sl.spec[2] + off;
     C* const gv = reinterpret_cast<C*>(sl.v[2]) + off;
@@ -647,7 +668,7 @@ k_axis_y_vel(AxisArgs<T> a) {
     }
     const T lz = gld(a.tb.pml_s[2] + z);
     __syncthreads();
-    y_vel_update<T, L, TW, NT>(buf, twl, vs, nullptr, lz, a.vcoef, gv, gr, px, ncol);
+    y_vel_update<T, L, TW, NT, PL>(buf, twl, vs, nullptr, lz, a.vcoef, gv, gr, px, ncol);
   }
 }
 
@@ -853,7 +874,7 @@ template <typename T> struct XArgs {
 // v_x <- L^s_x (L^s_x v_x - dt/rho0 d+_x p) with L^s_x varying along x (Alg. 1
 // momentum step), R2C of v_x into field 0.  (v_y and v_z are advanced by the
 // inverse y pass, k_axis_y_vel.)
-template <typename T, int M>
+template <typename T, int M, int PL = 0>
 __global__ void __launch_bounds__(X_NT) __attribute__((amdgpu_waves_per_eu(4))) k_x_velocity(XArgs<T> a) {
   using C = cplx<T>;
   constexpr int LPB = x_lpb_vel<T>(M);
@@ -888,7 +909,7 @@ __global__ void __launch_bounds__(X_NT) __attribute__((amdgpu_waves_per_eu(4))) 
   __syncthreads();
   c2r_pre<T, M, TWP, NC>(buf, twl + M);
   __syncthreads();
-  lds_fft<T, M, NC, TWP, X_NT, true>(buf, twl);
+  lds_fft<T, M, NC, TWP, X_NT, true, PL>(buf, twl);
   lanes2d<LPB, M>([&](int i, int l, int n) {
     if (l >= nl) return;
     const C dp = buf[n * TWP + l];
@@ -898,7 +919,7 @@ __global__ void __launch_bounds__(X_NT) __attribute__((amdgpu_waves_per_eu(4))) 
     buf[n * TWP + l] = vn;
   });
   __syncthreads();
-  lds_fft<T, M, NC, TWP, X_NT, false>(buf, twl);
+  lds_fft<T, M, NC, TWP, X_NT, false, PL>(buf, twl);
   r2c_post<T, M, TWP, NC>(buf, twl + M);
   __syncthreads();
   x_store_spectra<T, M, LPB, TWP, 1>(buf, sl.spec, 0, l0, nl, px);
@@ -988,7 +1009,7 @@ __device__ __forceinline__ int local_line(const int32_t* off, int l0, int nl, in
 // pcol + LPB receives d = rho0 sum_a d-_a v_a (0 without a density step), and
 // s is also stored as a real field in the slot's third spectrum buffer (rows
 // of px complex), for the lossy equation of state.
-template <typename T, int M, int LPB, int TWP, int TWPP, int KIND, bool STAGE_TW, bool LOSSY = false>
+template <typename T, int M, int LPB, int TWP, int TWPP, int KIND, bool STAGE_TW, bool LOSSY = false, int PL = 0>
 __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx& si, const Slot<T>& sl, int b,
                                                int l0, int nl, int state_mode, int pcol, cplx<T>* buf,
                                                cplx<T>* bufp, cplx<T>* spv, uint8_t* spm, cplx<T>* twl) {
@@ -1070,7 +1091,7 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx
   if (!no_step) {
     c2r_pre<T, M, TWP, NC>(buf, twl + M);
     __syncthreads();
-    lds_fft<T, M, NC, TWP, X_NT, true>(buf, twl);
+    lds_fft<T, M, NC, TWP, X_NT, true, PL>(buf, twl);
   } else {
     __syncthreads();
   }
@@ -1130,7 +1151,7 @@ __device__ __forceinline__ T p_at(const cplx<T>* bufp, int pcol, int l, int x) {
 //              from the tape), gradient accumulation, TR ring update
 //   XM_TRONLY  TR slot only (initial state and the TR pre-step), ring update
 //   XM_ADJONLY adjoint slot and gradient with p_tr = 0 (last two iterations)
-template <typename T, int M, int MODE>
+template <typename T, int M, int MODE, int PL = 0>
 __global__ void __launch_bounds__(X_NT) k_x_density(X2Args<T> a) {
   using C = cplx<T>;
   constexpr int LPB = x_lpb_den<T>(M);
@@ -1154,7 +1175,7 @@ __global__ void __launch_bounds__(X_NT) k_x_density(X2Args<T> a) {
   const StepIdx si = step_indices<T, MODE>(a);
 
   if (MODE == XM_FWD) {
-    density_update<T, M, LPB, TWP, TWPP, SP_SOURCE, true>(a, si, s_tr, b, l0, nl, 0, PA, buf, bufp, spv, spm,
+    density_update<T, M, LPB, TWP, TWPP, SP_SOURCE, true, false, PL>(a, si, s_tr, b, l0, nl, 0, PA, buf, bufp, spv, spm,
                                                           twl);
     // sensors f^n = M p and boundary tape g^n = p(dGamma)
     const int i0 = a.g.rec_off[l0], i1 = a.g.rec_off[l0 + nl];
@@ -1173,11 +1194,11 @@ __global__ void __launch_bounds__(X_NT) k_x_density(X2Args<T> a) {
     }
   }
   if (MODE == XM_PAIR || MODE == XM_ADJONLY) {
-    density_update<T, M, LPB, TWP, TWPP, SP_ADJOINT, true>(a, si, s_adj, b, l0, nl, 0, PA, buf, bufp, spv,
+    density_update<T, M, LPB, TWP, TWPP, SP_ADJOINT, true, false, PL>(a, si, s_adj, b, l0, nl, 0, PA, buf, bufp, spv,
                                                            spm, twl);
   }
   if (MODE == XM_PAIR || MODE == XM_TRONLY) {
-    density_update<T, M, LPB, TWP, TWPP, SP_DIRICHLET, MODE == XM_TRONLY>(a, si, s_tr, b, l0, nl, a.tr_state_mode,
+    density_update<T, M, LPB, TWP, TWPP, SP_DIRICHLET, MODE == XM_TRONLY, false, PL>(a, si, s_tr, b, l0, nl, a.tr_state_mode,
                                                                           PT, buf, bufp, spv, spm, twl);
   }
   if (MODE != XM_FWD) {
@@ -1205,7 +1226,7 @@ __global__ void __launch_bounds__(X_NT) k_x_density(X2Args<T> a) {
   }
   __syncthreads();
   // forward x-transform of the new pressure(s)
-  lds_fft<T, M, TWPP, TWPP, X_NT, false>(bufp, twl);
+  lds_fft<T, M, TWPP, TWPP, X_NT, false, PL>(bufp, twl);
   r2c_post<T, M, TWPP, TWPP>(bufp, twl + M);
   __syncthreads();
   if (NP == 2) {
@@ -1393,13 +1414,22 @@ __global__ void k_scale(T* p, long long n, T v) {
     p[i] *= v;
 }
 
+// Sum of v over the 64 lanes of a wavefront by butterfly shuffles (every
+// lane ends with the same sum; the pairing order is fixed: deterministic).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 // Residual r^n = f^n - f^delta_n (or a given residual), adjoint source
-// a^j = sum_{i<=j} r^{N-1-i} and per-block FP64 partial sums of r^2.
+// a^j = sum_{i<=j} r^{N-1-i} and per-block FP64 partial sums of r^2
+// (wavefront shuffles, then the four wavefront sums in order).
 // grid: x over receivers (256 per block), y over problems.
 template <typename T>
 __global__ void __launch_bounds__(256) k_residual(const T* traces, const T* obs, int obs_is_residual, T* adj,
                                                   double* partial, int nt, int n_rec) {
-  __shared__ double red[256];
+  __shared__ double red[4];
   const int b = blockIdx.y;
   const int r = blockIdx.x * 256 + threadIdx.x;
   double s2 = 0.0;
@@ -1414,13 +1444,10 @@ __global__ void __launch_bounds__(256) k_residual(const T* traces, const T* obs,
       adj[base + (size_t)j * n_rec + r] = (T)acc;
     }
   }
-  red[threadIdx.x] = s2;
+  s2 = wave_sum(s2);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s2;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partial[(size_t)b * gridDim.x + blockIdx.x] = red[0];
+  if (threadIdx.x == 0) partial[(size_t)b * gridDim.x + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 static __global__ void k_misfit_final(const double* partial, int nblk, double* misfit, int B) {

@@ -239,11 +239,13 @@ class Handle:
         return out
 
     # ------------------------------------------------------------------
-    TUNING_FIELDS = ("y_tile_bytes", "zm_tile_bytes", "zp_tile_bytes")
+    TUNING_FIELDS = ("y_tile_bytes", "zm_tile_bytes", "zp_tile_bytes", "y_plan", "zm_plan", "zp_plan", "x_plan")
 
     @property
     def tuning(self) -> dict:
-        """Launch tuning: {'y_tile_bytes', 'zm_tile_bytes', 'zp_tile_bytes'} (64 or 128)."""
+        """Launch tuning: tile row segments {'y_tile_bytes', 'zm_tile_bytes',
+        'zp_tile_bytes'} (64 or 128) and radix plans {'y_plan', 'zm_plan',
+        'zp_plan', 'x_plan'} (0 or 1) of the pass kinds (fwi_tuning)."""
         t = L.FwiTuning()
         _check(self._lib.fwi_get_tuning(self._h, ctypes.byref(t)), "fwi_get_tuning")
         return {f: int(getattr(t, f)) for f in self.TUNING_FIELDS}

@@ -4,19 +4,26 @@ Requests (a forward simulation or an encoded TR gradient on one of the
 configured grid levels, e.g. the levels of a coarse-to-fine multigrid scheme,
 Sec. 3.3) arrive at any time.  Each level keeps resident handles of batch
 capacity ``Level.batch`` on the device (fields, spectra, tape stay allocated
-between requests).  Whenever a solver slot is free, the dispatcher takes the
-oldest waiting request together with the later waiting requests of the same
-level and kind, up to the capacity, and runs them as ONE batched call: every
-pass launch of that call covers all of them.  Requests that arrive while
-others are on the GPU are admitted as soon as a slot and device memory free
-up (a new handle is created when its ``fwi_workspace_bytes`` footprint fits
-the HBM budget, evicting idle handles of other levels if needed); admitted
-calls run on their own HIP streams from worker threads, so their kernels
-overlap on the device with the calls already running.
+between requests).  Whenever one of ``max_inflight`` call slots is free, the
+dispatcher takes the oldest waiting request together with the later waiting
+requests of the same level and kind, up to the capacity, and enqueues them as
+ONE batched call: every pass launch of that call covers all of them, and its
+time step is replayed as a hipGraph.  Requests that arrive while others are
+on the GPU are admitted as soon as a slot and device memory free up (a new
+handle is created when its ``fwi_workspace_bytes`` footprint fits the HBM
+budget, evicting idle handles of other levels if needed).
+
+One dispatcher thread makes every GPU call of the server: the library's
+calls are asynchronous, so the dispatcher enqueues each batched call on its
+own HIP stream, records an event behind it and goes on admitting; calls on
+different streams overlap on the device, and a request's future is resolved
+when its call's event has completed.  (Keeping all GPU work of the server in
+one thread also keeps the step-graph captures free of other threads'
+synchronous copies, which invalidate a capture.)
 
 Results are identical to a solve run alone: every kernel is deterministic, a
-batched call computes each problem exactly as a batch-1 call does, and a
-handle serves one call at a time.
+batched call computes each problem exactly as a batch-1 call does, graph
+replay equals eager launches, and a handle serves one call at a time.
 
 Per-request latency runs from arrival to result; ``stats()`` reports
 p50 / p99 latency, the aggregate throughput in Mcell-steps/s (a forward solve
@@ -42,16 +49,15 @@ from . import fwi
 @dataclasses.dataclass
 class Level:
     """One grid level: handle arguments (``fwi.problem_kwargs``), the number of
-    requests one batched call may hold (the handles' batch capacity), and an
-    optional launch tuning (e.g. from ``autotune.apply``) set on every handle
-    of the level.  Served calls launch their passes eagerly: a step-graph
-    capture (FWI_GRAPH) on one worker's stream is invalidated when another
-    worker makes a synchronous copy or creates a handle meanwhile."""
+    requests one batched call may hold (the handles' batch capacity), whether
+    calls replay their time step as a hipGraph, and an optional launch tuning
+    (e.g. from ``autotune.apply``) set on every handle of the level."""
 
     name: str
     kwargs: dict
     tuning: Optional[dict] = None
     batch: int = 4
+    graph: bool = True
 
     @property
     def n_cells(self) -> int:
@@ -79,6 +85,21 @@ class _Request:
     t_done: float = 0.0
 
 
+@dataclasses.dataclass
+class _Call:
+    """One enqueued batched call: its requests, handle, stream and completion event."""
+
+    group: List[_Request]
+    level: str
+    handle: Optional[fwi.Handle]
+    reserved: bool
+    evict: List[fwi.Handle]
+    sidx: int
+    event: Optional[torch.cuda.Event] = None
+    outs: Optional[list] = None
+    error: Optional[BaseException] = None
+
+
 class Server:
     def __init__(self, levels: List[Level], budget_bytes: int, max_inflight: int = 4, device: int = 0):
         self.levels: Dict[str, Level] = {lv.name: lv for lv in levels}
@@ -95,12 +116,11 @@ class Server:
         self._idle: Dict[str, List[fwi.Handle]] = collections.defaultdict(list)
         self._all_handles: List[fwi.Handle] = []
         self._used = 0                  # bytes of resident and reserved handles
-        self._inflight = 0
+        self._inflight: List[_Call] = []
         self._pending: collections.deque = collections.deque()
         self._done: List[_Request] = []
         self._calls = 0
         self._lock = threading.Condition()
-        self._pool = cf.ThreadPoolExecutor(max_workers=self.max_inflight)
         self._streams = [torch.cuda.Stream(device=self.device) for _ in range(self.max_inflight)]
         self._free_streams = list(range(self.max_inflight))
         self._rid = 0
@@ -155,7 +175,6 @@ class Server:
             self._stop = True
             self._lock.notify_all()
         self._dispatcher.join()
-        self._pool.shutdown(wait=True)
         for h in self._all_handles:
             h.close()
         self._all_handles.clear()
@@ -216,52 +235,69 @@ class Server:
         self._used += fp
         return None, True, evict
 
-    def _dispatch(self) -> None:
-        with self._lock:
-            while not self._stop:
-                admitted = False
-                if not self._paused and self._inflight < self.max_inflight and self._pending:
-                    seen = set()
-                    for head in list(self._pending):
-                        key = (head.level, head.kind)
-                        if key in seen:
-                            continue
-                        seen.add(key)
-                        got = self._reserve(head.level)
-                        if got is None:
-                            continue
-                        cap = self.levels[head.level].batch
-                        group = [r for r in self._pending if (r.level, r.kind) == key][:cap]
-                        for r in group:
-                            self._pending.remove(r)
-                        self._inflight += 1
-                        self._calls += 1
-                        sidx = self._free_streams.pop()
-                        now = time.perf_counter()
-                        for r in group:
-                            r.t_start = now
-                        self._pool.submit(self._run, group, got, sidx)
-                        admitted = True
-                        break
-                if not admitted:
-                    self._lock.wait(0.01)
+    def _admit(self) -> List[_Call]:
+        """Under the lock: the calls to enqueue now (groups of waiting
+        requests with a handle or a reservation each, and a stream)."""
+        calls: List[_Call] = []
+        if self._paused:
+            return calls
+        while len(self._inflight) + len(calls) < self.max_inflight and self._pending:
+            admitted = None
+            seen = set()
+            for head in self._pending:
+                key = (head.level, head.kind)
+                if key in seen:
+                    continue
+                seen.add(key)
+                got = self._reserve(head.level)
+                if got is not None:
+                    cap = self.levels[head.level].batch
+                    group = [r for r in self._pending if (r.level, r.kind) == key][:cap]
+                    admitted = _Call(group, head.level, got[0], got[1], got[2], self._free_streams.pop())
+                    break
+            if admitted is None:
+                break
+            now = time.perf_counter()
+            for r in admitted.group:
+                self._pending.remove(r)
+                r.t_start = now
+            self._calls += 1
+            calls.append(admitted)
+        self._inflight.extend(calls)
+        return calls
 
-    def _run(self, group: List[_Request], got, sidx: int) -> None:
-        h, reserved, evict = got
-        lv = self.levels[group[0].level]
-        stream = self._streams[sidx]
-        error = None
-        outs = None
-        try:
-            for e in evict:
-                e.close()
-            if h is None:
-                h = fwi.Handle(**lv.kwargs, batch=lv.batch, device=self.device.index or 0)
-                if lv.tuning:
-                    h.tuning = lv.tuning
+    def _dispatch(self) -> None:
+        while True:
+            with self._lock:
+                if self._stop and not self._pending and not self._inflight:
+                    return
+                calls = self._admit()
+            for call in calls:
+                self._enqueue(call)
+            finished = [c for c in list(self._inflight) if c.error is not None or c.event.query()]
+            for call in finished:
+                self._finish(call)
+            if not calls and not finished:
                 with self._lock:
-                    self._all_handles.append(h)
-            h.use_graph = False
+                    self._lock.wait(0.0005 if self._inflight else 0.01)
+
+    def _enqueue(self, call: _Call) -> None:
+        """Create the handle if reserved, copy the inputs and enqueue the
+        batched call on the call's stream (asynchronous), then its event."""
+        lv = self.levels[call.level]
+        group = call.group
+        stream = self._streams[call.sidx]
+        try:
+            for e in call.evict:
+                e.close()
+            if call.handle is None:
+                call.handle = fwi.Handle(**lv.kwargs, batch=lv.batch, device=self.device.index or 0)
+                if lv.tuning:
+                    call.handle.tuning = lv.tuning
+                with self._lock:
+                    self._all_handles.append(call.handle)
+            h = call.handle
+            h.use_graph = lv.graph
             with torch.cuda.stream(stream):
                 for r in group:
                     if r.ready is not None:
@@ -271,29 +307,32 @@ class Server:
                 w = torch.stack([torch.as_tensor(r.w).to(h.device, torch.int8) for r in group])
                 if group[0].kind == "forward":
                     tr = h.forward(c, src, w)
-                    outs = [tr[b:b + 1].clone() for b in range(len(group))]
+                    call.outs = [tr[b:b + 1].clone() for b in range(len(group))]
                 else:
                     obs = torch.stack([torch.as_tensor(r.obs).to(h.device, h.dtype) for r in group])
                     mis, grad = h.gradient(c, src, w, obs)
-                    outs = [(mis[b:b + 1].clone(), grad[b:b + 1].clone()) for b in range(len(group))]
-                stream.synchronize()
+                    call.outs = [(mis[b:b + 1].clone(), grad[b:b + 1].clone()) for b in range(len(group))]
+                call.event = torch.cuda.Event()
+                call.event.record(stream)
         except Exception as e:  # noqa: BLE001 - reported through the futures
-            error = e
+            call.error = e
+
+    def _finish(self, call: _Call) -> None:
         t_done = time.perf_counter()
         with self._lock:
-            if h is not None:
-                self._idle[lv.name].append(h)
-            elif reserved:
-                self._used -= self.footprint[lv.name]   # creation failed: release the reservation
-            self._free_streams.append(sidx)
-            self._inflight -= 1
-            for r in group:
+            self._inflight.remove(call)
+            if call.handle is not None:
+                self._idle[call.level].append(call.handle)
+            elif call.reserved:
+                self._used -= self.footprint[call.level]   # creation failed: release the reservation
+            self._free_streams.append(call.sidx)
+            for r in call.group:
                 r.t_done = t_done
-                if error is None:
+                if call.error is None:
                     self._done.append(r)
             self._lock.notify_all()
-        for b, r in enumerate(group):
-            if error is None:
-                r.future.set_result(outs[b])
+        for b, r in enumerate(call.group):
+            if call.error is None:
+                r.future.set_result(call.outs[b])
             else:
-                r.future.set_exception(error)
+                r.future.set_exception(call.error)

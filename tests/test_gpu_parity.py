@@ -49,6 +49,76 @@ def test_derivative_matches_oracle(shape, precision, tol):
     h.close()
 
 
+# every FFT length added for larger and PML-padded grids (192, 240, 320, 384,
+# 480, 512) on every axis it can take: x (as nx/2), y and z
+LONG_SHAPES = [(16, 192, 480), (320, 16, 768), (16, 480, 1024), (512, 16, 640), (240, 384, 16)]
+
+
+@pytest.mark.parametrize("precision,tol", [(8, 1e-12), (4, 2e-6)])
+@pytest.mark.parametrize("shape", LONG_SHAPES)
+def test_derivative_long_lengths_match_oracle(shape, precision, tol):
+    print(f"derivative shape={shape} precision={precision}", flush=True)
+    prob = make_small(shape=shape, nt=2, precision=precision, r_transducer=5.0, r_gamma=3.0)
+    h = handle(prob, precision)
+    sch = ks.scheme_for(prob)
+    rng = np.random.default_rng(4)
+    g = rng.standard_normal(shape)
+    for axis in range(3):
+        for sign in (+1, -1):
+            got = h.derivative(torch.from_numpy(g), axis, sign).cpu().numpy()
+            want = sch.d_plus(g, axis) if sign > 0 else sch.d_minus(g, axis)
+            assert rel(got, want) < tol, (axis, sign, rel(got, want))
+    h.close()
+
+
+def test_long_length_gradient_matches_oracle():
+    # a TR gradient whose x passes run at nx/2 = 240 and y passes at 192
+    shape = (24, 192, 480)
+    prob = make_small(shape=shape, nt=24, n_src=2, n_rec=12, layer=2, precision=8, r_transducer=8.0,
+                      r_gamma=5.0)
+    print(f"gradient shape={shape}", flush=True)
+    sch = ks.scheme_for(prob)
+    w, S = _inputs(prob)
+    obs = random_traces(prob.nt, prob.n_rec, seed=5, scale=1e-3)
+    D, G, _ = ks.tr_gradient(sch, prob.c_eval, prob.src_ijk, S, w, prob.rec_ijk, obs, prob.gamma, prob.boundary,
+                             prob.nt)
+    traces = ks.forward(sch, prob.c_eval, prob.src_ijk, S, w, prob.rec_ijk, prob.nt)["traces"]
+    h = handle(prob, 8)
+    got_tr = h.forward(torch.from_numpy(prob.c_eval), torch.from_numpy(S), torch.from_numpy(w))[0].cpu().numpy()
+    assert rel(got_tr, traces) < 1e-10
+    mis, grad = h.gradient(torch.from_numpy(prob.c_eval), torch.from_numpy(S), torch.from_numpy(w),
+                           torch.from_numpy(obs))
+    g = prob.gamma.astype(bool)
+    assert abs(float(mis[0]) - D) <= 1e-10 * D
+    assert rel(grad[0].cpu().numpy()[g], G[g]) < 1e-9
+    h.close()
+
+
+@pytest.mark.parametrize("precision,ttol,gtol", [(8, 1e-10, 1e-9), (4, 1e-4, 1e-3)])
+@pytest.mark.parametrize("shape", [(32, 32, 64), (32, 96, 448)])
+def test_radix_plan_1_matches_oracle(shape, precision, ttol, gtol):
+    # every pass kind with radix plan 1, on lengths whose two plans differ:
+    # 32 (8*4 / 4*8), 96 (3*8*4 / 3*4*8) and nx/2 = 224 (the full-size x length)
+    print(f"radix plan 1 shape={shape} precision={precision}", flush=True)
+    prob = make_small(shape=shape, nt=30, n_src=2, n_rec=12, layer=2, precision=precision)
+    w, S = _inputs(prob)
+    sch = ks.scheme_for(prob)
+    obs = random_traces(prob.nt, prob.n_rec, seed=6, scale=1e-3)   # a residual large against rounding
+    traces = ks.forward(sch, prob.c_eval, prob.src_ijk, S, w, prob.rec_ijk, prob.nt)["traces"]
+    D, G, _ = ks.tr_gradient(sch, prob.c_eval, prob.src_ijk, S, w, prob.rec_ijk, obs, prob.gamma,
+                             prob.boundary, prob.nt)
+    h = handle(prob, precision)
+    h.tuning = {"y_plan": 1, "zm_plan": 1, "zp_plan": 1, "x_plan": 1}
+    got_tr = h.forward(torch.from_numpy(prob.c_eval), torch.from_numpy(S), torch.from_numpy(w))[0].cpu().numpy()
+    assert rel(got_tr, traces) < ttol
+    mis, grad = h.gradient(torch.from_numpy(prob.c_eval), torch.from_numpy(S), torch.from_numpy(w),
+                           torch.from_numpy(obs))
+    assert abs(float(mis[0]) - D) <= ttol * D
+    gmask = prob.gamma.astype(bool)
+    assert rel(grad[0].cpu().numpy()[gmask], G[gmask]) < gtol
+    h.close()
+
+
 def _inputs(prob, seed=0):
     w = oracle.rademacher(prob.enc_seed, prob.n_src)
     S = prob.src_signals()
