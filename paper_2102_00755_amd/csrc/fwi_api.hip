@@ -574,8 +574,6 @@ template <typename T> struct Engine : EngineBase {
     const int ty = tile_bytes[AK_Y], tzm = tile_bytes[AK_ZMINUS], tzp = tile_bytes[AK_ZPLUS];
     const dim3 gy(ntx(AK_Y) * d.nz, nslots * 1), gy3(ntx(AK_Y) * d.nz, nslots * 3);
     const dim3 gz(ntx(AK_ZPLUS) * d.ny, nslots), gz3(ntx(AK_ZMINUS) * d.ny, nslots * 3);
-    const int tyv = FWI_YV_TILE_BYTES > 0 ? FWI_YV_TILE_BYTES : ty;
-    const dim3 gyv((d.px + tyv / (int)sizeof(C) - 1) / (tyv / (int)sizeof(C)) * d.nz, nslots);
     const double S = sbytes(), F = fbytes(), ns = nslots;
     hipEvent_t ev;
     ev = timer.begin(st);
@@ -585,10 +583,10 @@ template <typename T> struct Engine : EngineBase {
     FWI_HIP(launch_axis_zp<T>(d.nz, tzp, plans[AK_ZPLUS], gz, st, axis_args(slot0, na, slot1, 1, 0)));        // Z2
     timer.end(ev, FWI_PASS_Z_PLUS, 3 * ns * S, st);
     ev = timer.begin(st);
-    FWI_HIP(launch_axis_yv<T>(d.ny, 0, tyv, plans[AK_Y], gyv, st, axis_args(slot0, na, slot1, 1, 0)));    // Y4: Q, v_y
+    FWI_HIP(launch_axis_yv<T>(d.ny, 0, ty, plans[AK_Y], gy, st, axis_args(slot0, na, slot1, 1, 0)));    // Y4: Q, v_y
     timer.end(ev, FWI_PASS_Y_VEL_Q, 5 * ns * S, st);
     ev = timer.begin(st);
-    FWI_HIP(launch_axis_yv<T>(d.ny, 1, tyv, plans[AK_Y], gyv, st, axis_args(slot0, na, slot1, 1, 0)));    // Y4: R, v_z
+    FWI_HIP(launch_axis_yv<T>(d.ny, 1, ty, plans[AK_Y], gy, st, axis_args(slot0, na, slot1, 1, 0)));    // Y4: R, v_z
     timer.end(ev, FWI_PASS_Y_VEL_R, 4 * ns * S, st);
     XArgs<T> xa;
     xa.slots = slot_table; xa.slot0 = slot0; xa.na = na; xa.slot1 = slot1;

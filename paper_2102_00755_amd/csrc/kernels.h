@@ -67,13 +67,6 @@ namespace fwi {
 #ifndef FWI_XEOS_LDS_BUDGET
 #define FWI_XEOS_LDS_BUDGET 3072
 #endif
-// FWI_YV_TILE_BYTES    row segment of the tiles of the two y passes with the
-//                      velocity updates (0: the y-pass tuning)
-// FWI_Z_MIN_WAVES      waves per SIMD the z passes are compiled for (0: the
-//                      compiler's choice)
-#ifndef FWI_YV_TILE_BYTES
-#define FWI_YV_TILE_BYTES 0
-#endif
 // FWI_Y_PLAN, FWI_ZM_PLAN, FWI_ZP_PLAN, FWI_X_PLAN
 //                      default radix plans (make_plan: 0 or 1) of the y passes,
 //                      Z1, Z2 and the velocity / density x passes.  At
@@ -94,14 +87,6 @@ namespace fwi {
 #endif
 #ifndef FWI_X_PLAN
 #define FWI_X_PLAN 0
-#endif
-#ifndef FWI_Z_MIN_WAVES
-#define FWI_Z_MIN_WAVES 0
-#endif
-#if FWI_Z_MIN_WAVES > 0
-#define FWI_Z_WAVES_ATTR __attribute__((amdgpu_waves_per_eu(FWI_Z_MIN_WAVES)))
-#else
-#define FWI_Z_WAVES_ATTR
 #endif
 enum AxisKind { AK_Y = 0, AK_ZMINUS = 1, AK_ZPLUS = 2 };
 // axis-pass tile width in complex elements for a row segment of TB bytes
@@ -359,7 +344,7 @@ __device__ __forceinline__ void z_apply(cplx<T>* buf, const cplx<T>* m, const cp
 // Z pass of the velocity divergence terms: field f -> F_z^-1 m-_f F_z field f
 // (eq. DisPartDevSt with the minus shift).  L == nz.
 template <typename T, int L, int TB, int PL = 0>
-__global__ void __launch_bounds__(axis_nt(L, tile_tw<T, TB>())) FWI_Z_WAVES_ATTR
+__global__ void __launch_bounds__(axis_nt(L, tile_tw<T, TB>()))
 k_axis_z_minus(AxisArgs<T> a) {
   using C = cplx<T>;
   constexpr int TW = tile_tw<T, TB>();
@@ -399,7 +384,7 @@ k_axis_z_minus(AxisArgs<T> a) {
 // numbers are at hand: one spectrum less is written here and read there.
 // L == nz.
 template <typename T, int L, int TB, int PL = 0>
-__global__ void __launch_bounds__(axis_nt(L, tile_tw<T, TB>())) FWI_Z_WAVES_ATTR
+__global__ void __launch_bounds__(axis_nt(L, tile_tw<T, TB>()))
 k_axis_z_plus(AxisArgs<T> a) {
   using C = cplx<T>;
   constexpr int TW = tile_tw<T, TB>();
