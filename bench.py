@@ -31,16 +31,49 @@ PEAK_HBM_GBS = 8000.0
 STEP_BYTES_PER_CELL = 172.0
 
 KERNEL_SYMBOLS = {
-    "y_fwd": "k_axis_y<float, {ny}, false, {ty}>",
-    "y_inv": "k_axis_y<float, {ny}, true, {ty}>",
-    "z_plus": "k_axis_z_plus<float, {nz}, {tzp}>",
-    "z_minus": "k_axis_z_minus<float, {nz}, {tzm}>",
-    "x_vel": "k_x_velocity<float, {m}>",
-    "x_den_fwd": "k_x_density<float, {m}, 0>",
-    "x_den_pair": "k_x_density<float, {m}, 1>",
-    "y_vel_q": "k_axis_y_vel<float, {ny}, {ty}, 0>",
-    "y_vel_r": "k_axis_y_vel<float, {ny}, {ty}, 1>",
+    "y_fwd": "k_axis_y<float, {ny}, false, {ty}, {py}>",
+    "y_inv": "k_axis_y<float, {ny}, true, {ty}, {py}>",
+    "z_plus": "k_axis_z_plus<float, {nz}, {tzp}, {pzp}>",
+    "z_minus": "k_axis_z_minus<float, {nz}, {tzm}, {pzm}>",
+    "x_vel": "k_x_velocity<float, {m}, {px}>",
+    "x_den_fwd": "k_x_density<float, {m}, 0, {px}>",
+    "x_den_pair": "k_x_density<float, {m}, 1, {px}>",
+    "y_vel_q": "k_axis_y_vel<float, {ny}, {ty}, 0, {py}>",
+    "y_vel_r": "k_axis_y_vel<float, {ny}, {ty}, 1, {py}>",
 }
+
+
+def _plan_run(L: int, plan: int) -> int:
+    """The radix plan a kernel of length L is instantiated with for the
+    requested plan: 1 only where the power-of-two stages of the length are
+    not a palindrome (otherwise both plans are the same kernel, plan 0)."""
+    m = L
+    for r in (7, 5, 3):
+        while m % r == 0:
+            m //= r
+    pw = []
+    while m > 1:
+        if m == 16:
+            pw += [4, 4]
+            m = 1
+        elif m % 8 == 0:
+            pw.append(8)
+            m //= 8
+        elif m % 4 == 0:
+            pw.append(4)
+            m //= 4
+        else:
+            pw.append(2)
+            m //= 2
+    return plan if pw != pw[::-1] else 0
+
+
+def kernel_symbol(name: str, nx: int, ny: int, nz: int, tuning: dict) -> str:
+    """Demangled symbol of the kernel that runs pass `name` under `tuning`."""
+    return KERNEL_SYMBOLS[name].format(
+        nx=nx, ny=ny, nz=nz, m=nx // 2, ty=tuning["y_tile_bytes"], tzm=tuning["zm_tile_bytes"],
+        tzp=tuning["zp_tile_bytes"], py=_plan_run(ny, tuning["y_plan"]), pzm=_plan_run(nz, tuning["zm_plan"]),
+        pzp=_plan_run(nz, tuning["zp_plan"]), px=_plan_run(nx // 2, tuning["x_plan"]))
 
 
 def measured_traffic(kernel: str, bytes_per_launch: float):
@@ -221,7 +254,6 @@ def main():
                               "bytes_per_launch": by / n}
     dom = max(per_pass, key=lambda k: per_pass[k]["avg_ms"] * passes[k][0]) if per_pass else None
     tn = h.tuning
-    tiles = dict(ty=tn["y_tile_bytes"], tzm=tn["zm_tile_bytes"], tzp=tn["zp_tile_bytes"])
     roof = None
     if dom:
         d = per_pass[dom]
@@ -231,9 +263,8 @@ def main():
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": round(d["GB/s"] / PEAK_HBM_GBS, 4),
-            "traffic": measured_traffic(KERNEL_SYMBOLS[dom].format(nx=nx, ny=ny, nz=nz, m=nx // 2, **tiles),
-                                        d["bytes_per_launch"]),
-            "kernel": KERNEL_SYMBOLS[dom].format(nx=nx, ny=ny, nz=nz, m=nx // 2, **tiles),
+            "traffic": measured_traffic(kernel_symbol(dom, nx, ny, nz, tn), d["bytes_per_launch"]),
+            "kernel": kernel_symbol(dom, nx, ny, nz, tn),
             "avg_ms": round(d["avg_ms"], 4),
             "bytes_per_launch": d["bytes_per_launch"],
         }
