@@ -65,11 +65,23 @@ enum {
   FWI_GRAPH = 16,         /* capture one time step in a hipGraph and replay it
                              (step index read from device memory); results
                              are identical to eager launches                 */
-  FWI_MEAN = 32           /* fwi_gradient / fwi_backward: write the mean of the
+  FWI_MEAN = 32,          /* fwi_gradient / fwi_backward: write the mean of the
                              B gradients, (1/B) sum_b G_b summed in FP64 in the
                              order b = 0..B-1, to ONE grid [nz][ny][nx]
                              (averaging of independent encoded realisations,
                              Sec. 3.2); misfit stays [B]                     */
+  FWI_EXACT = 64          /* fwi_gradient: the exact discrete gradient dD/dc0
+                             on Gamma instead of Alg. 1's TR gradient:
+                             reverse-mode differentiation of every operation
+                             of the forward iteration (PML included; with
+                             absorption set, the dL/dc0 terms of App. A:
+                             dp/dc0 = (2/c0) p + c0^2 (tau' A[d] - eta' B[s])),
+                             from a history of dp/dc0 on Gamma stored by the
+                             forward run (nt x |Gamma| values of the handle's
+                             precision, allocated on first use: FWI_ERR_OOM).
+                             The c0 of the source scaling is held fixed.
+                             B = 1 only, without FWI_GRAPH, FWI_MEAN or
+                             FWI_TR_FINAL_STATE (FWI_ERR_INVALID_ARG)        */
 };
 
 /* Scheme parameters (App. B).  dt = cfl dx / c_max in the paper (Sec. 4.1). */

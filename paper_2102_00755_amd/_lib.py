@@ -29,6 +29,7 @@ FWI_CHECK_FINITE = 4
 FWI_TR_FINAL_STATE = 8
 FWI_GRAPH = 16
 FWI_MEAN = 32
+FWI_EXACT = 64
 
 FWI_NOALLOC_MAX_PAIRS = 256   # static scratch of fwi_lbfgs_apply_noalloc
 

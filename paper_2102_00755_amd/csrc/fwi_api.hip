@@ -13,6 +13,7 @@
 
 #include "../../include/fwi.h"
 #include "dispatch.h"
+#include "exact_kernels.h"
 #include "optim_kernels.h"
 
 using namespace fwi;
@@ -366,6 +367,10 @@ template <typename T> struct Engine : EngineBase {
   bool tr_flip = true;
   DevBuf mem_padj;
   T* padj = nullptr;
+  // exact gradient (FWI_EXACT): dp/dc0 history on Gamma [nt][n_gam] and the
+  // linear voxel index of every receiver (allocated on first use)
+  DevBuf mem_hist, mem_rec_lin;
+  T* hist_ptr = nullptr;          // non-null only during the forward of an exact gradient
 
   int init(const fwi_params& prm, Geometry&& g, int dev) {
     p = prm;
@@ -617,6 +622,7 @@ template <typename T> struct Engine : EngineBase {
     a.c = c;
     a.ring = ring; a.gacc = gacc;
     a.delay = delays_on ? delay : nullptr;
+    a.hist = hist_ptr;
     return a;
   }
   int launch_x2(int mode, int B, const X2Args<T>& a, hipStream_t st) {
@@ -1031,6 +1037,132 @@ template <typename T> struct Engine : EngineBase {
     return FWI_OK;
   }
 
+  // Fractional Laplacians of two real fields in one set of passes (the
+  // passes of the lossy equation of state): outB = B[inB] = F^-1 |k|^{y-1} F
+  // inB, outA = A[inA] = F^-1 |k|^{y-2} F inA (both 0 at k = 0).  Uses the
+  // spectra of the first forward slot.
+  int frac_pair(const T* inB, const T* inA, T* outB, T* outA, hipStream_t st) {
+    const int s = p.batch;
+    XArgs<T> xa;
+    xa.slots = slot_table; xa.slot0 = s; xa.na = 1; xa.slot1 = s;
+    xa.d = d; xa.tb = tb; xa.dt_rho = (T)0;
+    const int lpb = x_lines_per_block<T>(d.M);
+    const dim3 gx((d.nlines + lpb - 1) / lpb, 1);
+    const int ty = tile_bytes[AK_Y], tz = tile_bytes[AK_ZMINUS];
+    const AxisArgs<T> ax = axis_args(s, 1, s, 2, 0);
+    FWI_HIP(launch_x_r2c<T>(d.M, gx, st, xa, inB, 0));
+    FWI_HIP(launch_x_r2c<T>(d.M, gx, st, xa, inA, 1));
+    FWI_HIP(launch_axis_y<T>(d.ny, false, ty, plans[AK_Y], dim3(ntx(AK_Y) * d.nz, 2), st, ax));
+    FWI_HIP(launch_axis_zf<T>(d.nz, tz, plans[AK_ZMINUS], dim3(ntx(AK_ZMINUS) * d.ny, 2), st, ax));
+    FWI_HIP(launch_axis_y<T>(d.ny, true, ty, plans[AK_Y], dim3(ntx(AK_Y) * d.nz, 2), st, ax));
+    FWI_HIP(launch_x_c2r<T>(d.M, gx, st, xa, outB, 0, nullptr));
+    FWI_HIP(launch_x_c2r<T>(d.M, gx, st, xa, outA, 1, nullptr));
+    return FWI_OK;
+  }
+
+  // The exact discrete gradient of D (FWI_EXACT): the forward iteration with
+  // dp/dc0 at a fixed state stored on Gamma for every step, then reverse-mode
+  // differentiation of every operation of the iteration, backwards in time:
+  //   pb += M^T r^n;  G += pb * dp/dc0 (step n)
+  //   sb = c0^2 pb - B[eta c0^2 pb],  db = A[tau c0^2 pb]       (absorption)
+  //   rb_a += sb; t = L_a rb_a; rb_a = L_a t; vb_a -= d+_a (rho0 db - dt rho0 t)
+  //   t = Ls_a vb_a; vb_a = Ls_a t; pb = dt/rho0 sum_a d-_a t
+  // (d-^T = -d+, d+^T = -d-: the staggered multipliers are conjugate).  The
+  // c0 of the source scaling is held fixed (as in the oracle).  Problem 0 only.
+  int run_exact(const T* c, const T* src, const int8_t* w, const T* obs, bool is_resid, double* misfit, T* grad,
+                hipStream_t st) {
+    const int N = p.nt;
+    int rc;
+    if (!mem_hist.p) {
+      const size_t n = std::max<size_t>((size_t)N * std::max<long long>(d.n_gam, 1) * sizeof(T), 256);
+      if (hipMalloc(&mem_hist.p, n) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(FWI_ERR_OOM, "device allocation of " + std::to_string(n) + " bytes failed");
+      }
+    }
+    if (!mem_rec_lin.p) {
+      std::vector<int32_t> lin(std::max(d.n_rec, 1), 0);
+      for (int line = 0; line < d.nlines; ++line)
+        for (int i = geo.rec_off[line]; i < geo.rec_off[line + 1]; ++i)
+          lin[geo.rec_id[i]] = line * d.nx + geo.rec_x[i];
+      if (hipMalloc(&mem_rec_lin.p, lin.size() * 4) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(FWI_ERR_OOM, "receiver index allocation failed");
+      }
+      FWI_HIP(hipMemcpy(mem_rec_lin.p, lin.data(), lin.size() * 4, hipMemcpyHostToDevice));
+    }
+    T* hist = (T*)mem_hist.p;
+    const int32_t* rec_lin = (const int32_t*)mem_rec_lin.p;
+    // forward with the dp/dc0 history
+    hist_ptr = hist;
+    rc = run_forward(1, c, src, w, traces_int, false, st);
+    hist_ptr = nullptr;
+    if (rc) return rc;
+    // misfit (the reversed running sum the kernel also writes is not used here)
+    hipLaunchKernelGGL((k_residual<T>), dim3(nblk_rec, 1), dim3(256), 0, st, traces_int, obs, is_resid ? 1 : 0, adj,
+                       partial, N, d.n_rec);
+    FWI_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_misfit_final, dim3(1), dim3(64), 0, st, partial, nblk_rec, misfit, 1);
+    FWI_HIP(hipGetLastError());
+    // work fields: the adjoint slot and the real fields of the first forward
+    // slot (its spectra are the transforms' scratch)
+    const Slot<T>& s0 = slots_host[0];
+    const Slot<T>& sS = slots_host[p.batch];
+    T* vb[3] = {s0.rho[0], s0.rho[1], s0.rho[2]};
+    T* rb[3] = {s0.v[0], s0.v[1], s0.v[2]};
+    T* pb = (T*)s0.spec[0];
+    T* FB = (T*)s0.spec[1];
+    T* FA = (T*)s0.spec[2];
+    T* eP = sS.rho[0];
+    T* tP = sS.rho[1];
+    T* ub = sS.rho[2];
+    T* tmp = sS.v[0];
+    T* tv = sS.v[1];
+    const long long nf = d.nfield;
+    for (int a = 0; a < 3; ++a) {
+      if ((rc = fill<T>(vb[a], nf, (T)0, st))) return rc;
+      if ((rc = fill<T>(rb[a], nf, (T)0, st))) return rc;
+    }
+    if ((rc = fill<T>(pb, nf, (T)0, st))) return rc;
+    if ((rc = fill<double>(gacc, d.n_gam, 0.0, st))) return rc;
+    const int nb = (int)std::min<long long>((nf + 255) / 256, 16384);
+    const int gb = (int)std::max<long long>(1, std::min<long long>((d.n_gam + 255) / 256, 8192));
+    const T dt_rho0 = (T)(p.dt * p.rho0), rho0 = (T)p.rho0, dt_over_rho0 = (T)(p.dt / p.rho0);
+    for (int n = N - 1; n >= 0; --n) {
+      hipLaunchKernelGGL((k_ex_inject<T>), dim3((d.n_rec + 255) / 256 + 1), dim3(256), 0, st, pb, rec_lin,
+                         traces_int, obs, is_resid ? 1 : 0, n, d.n_rec);
+      FWI_HIP(hipGetLastError());
+      if (d.n_gam > 0) {
+        hipLaunchKernelGGL((k_ex_accum<T>), dim3(gb), dim3(256), 0, st, gacc, pb, gam_lin,
+                           hist + (size_t)n * d.n_gam, (int)d.n_gam);
+        FWI_HIP(hipGetLastError());
+      }
+      if (lossy) {
+        hipLaunchKernelGGL((k_ex_coef<T>), dim3(nb), dim3(256), 0, st, c, a0f, (T)a0u, ypow,
+                           2.0 * std::tan(kPi * ypow / 2.0), pb, eP, tP, nf);
+        FWI_HIP(hipGetLastError());
+        if ((rc = frac_pair(eP, tP, FB, FA, st))) return rc;
+      }
+      for (int a = 0; a < 3; ++a) {
+        hipLaunchKernelGGL((k_ex_rho<T>), dim3(nb), dim3(256), 0, st, c, pb, lossy ? FB : nullptr,
+                           lossy ? FA : nullptr, rb[a], ub, tb.pml_n[a], a, d, dt_rho0, rho0);
+        FWI_HIP(hipGetLastError());
+        if ((rc = derivative(ub, tmp, a, +1, st))) return rc;
+        hipLaunchKernelGGL((k_axpby<T>), dim3(nb), dim3(256), 0, st, nf, (T)-1, (const T*)tmp, (T)1, vb[a]);
+        FWI_HIP(hipGetLastError());
+      }
+      if ((rc = fill<T>(pb, nf, (T)0, st))) return rc;
+      for (int a = 0; a < 3; ++a) {
+        hipLaunchKernelGGL((k_ex_vel<T>), dim3(nb), dim3(256), 0, st, vb[a], tv, tb.pml_s[a], a, d);
+        FWI_HIP(hipGetLastError());
+        if ((rc = derivative(tv, tmp, a, -1, st))) return rc;
+        hipLaunchKernelGGL((k_axpby<T>), dim3(nb), dim3(256), 0, st, nf, dt_over_rho0, (const T*)tmp, (T)1, pb);
+        FWI_HIP(hipGetLastError());
+      }
+    }
+    return scatter_grad(1, grad, st);
+  }
+
   int gradient(int B, const void* c, const void* src, const int8_t* w, const void* obs, double* misfit,
                void* grad, int flags, hipStream_t st) override {
     int rc;
@@ -1043,6 +1175,16 @@ template <typename T> struct Engine : EngineBase {
     tape_valid = false;
     use_graph = (flags & FWI_GRAPH) != 0;
     mean_out = (flags & FWI_MEAN) != 0;
+    if (flags & FWI_EXACT) {
+      if (B != 1 || (flags & (FWI_GRAPH | FWI_MEAN | FWI_TR_FINAL_STATE)))
+        return fail(FWI_ERR_INVALID_ARG, "FWI_EXACT takes B = 1 without FWI_GRAPH, FWI_MEAN, FWI_TR_FINAL_STATE");
+      mean_out = false;
+      if ((rc = run_exact((const T*)c, (const T*)src, w, (const T*)obs, false, misfit, (T*)grad, st))) return rc;
+      FWI_HIP(timer.collect(st));
+      if (flags & FWI_CHECK_FINITE)
+        if ((rc = check_finite((const T*)grad, d.nfield, st))) return rc;
+      return FWI_OK;
+    }
     if ((rc = run_forward(B, (const T*)c, (const T*)src, w, traces_int, true, st))) return rc;
     if ((rc = run_adjoint_tr(B, (const T*)c, (const T*)obs, false, traces_int, misfit, (T*)grad,
                              (flags & FWI_TR_FINAL_STATE) != 0, st)))

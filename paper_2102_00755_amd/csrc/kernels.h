@@ -945,6 +945,9 @@ template <typename T> struct X2Args {
   T two_tan;             // 2 tan(pi y / 2)
   T tr_tau_sign;         // sign of tau in the TR simulation (-1: switched)
   T* padj;               // [B][n_gam]: adjoint pressure on Gamma of this step
+  // exact gradient: [nt][n_gam] dp/dc0 at fixed state on Gamma per forward
+  // step (problem 0), or null
+  T* hist;
 };
 
 // Per-launch step indices of an X2 launch.
@@ -1177,6 +1180,16 @@ __global__ void __launch_bounds__(X_NT) k_x_density(X2Args<T> a) {
         trow[i] = p_at<T, TWPP>(bufp, PA, l, a.g.bnd_x[i]);
       }
     }
+    if (a.hist) {
+      // exact gradient: dp/dc0 of p = c0^2 sum rho at a fixed state, (2/c0) p
+      const int j0 = a.g.gam_off[l0], j1 = a.g.gam_off[l0 + nl];
+      T* hrow = a.hist + (size_t)si.step * a.d.n_gam;
+      for (int i = j0 + (int)threadIdx.x; i < j1; i += X_NT) {
+        const int l = local_line(a.g.gam_off, l0, nl, i);
+        const int x = a.g.gam_x[i];
+        hrow[i] = (T)2 / a.c[(size_t)(l0 + l) * nx + x] * p_at<T, TWPP>(bufp, PA, l, x);
+      }
+    }
   }
   if (MODE == XM_PAIR || MODE == XM_ADJONLY) {
     density_update<T, M, LPB, TWP, TWPP, SP_ADJOINT, true, false, PL>(a, si, s_adj, b, l0, nl, 0, PA, buf, bufp, spv,
@@ -1312,13 +1325,34 @@ __global__ void __launch_bounds__(X_NT) k_x_lossy_eos(X2Args<T> a) {
     const T eta = a.two_tan * al * (c * cy1);
     return c * c * (s + sgn * tau * A - eta * B);
   };
+  // exact gradient: dp/dc0 at a fixed state, (2/c0) p + c0^2 (tau' A - eta' B)
+  // with tau' = -2 alpha0 (y-1) c0^{y-2}, eta' = 2 alpha0 y c0^{y-1} tan(pi y/2)
+  auto dpdc = [&](T p, T A, T B, T c, T al) -> T {
+    const T cy1 = real_pow(c, a.y1);               // c0^{y-1}
+    const T dtau = (T)-2 * al * a.y1 * cy1 / c;
+    const T deta = (a.y1 + (T)1) * a.two_tan * al * cy1;
+    return (T)2 / c * p + c * c * (dtau * A - deta * B);
+  };
+  const bool want_hist = KIND == SP_SOURCE && a.hist != nullptr;
   lanes2d<LPB, M>([&](int i, int l, int n) {
     if (l >= nl) return;
     const C Bv = buf[n * TWP + l];
     const C Av = buf[n * TWP + LPB + l];
-    buf[n * TWP + l] = cmake<C>(eos(ss[i].x, Av.x, Bv.x, cc[i].x, aa[i].x), eos(ss[i].y, Av.y, Bv.y, cc[i].y, aa[i].y));
+    const C pv = cmake<C>(eos(ss[i].x, Av.x, Bv.x, cc[i].x, aa[i].x), eos(ss[i].y, Av.y, Bv.y, cc[i].y, aa[i].y));
+    buf[n * TWP + l] = pv;
+    if (want_hist)   // A is not needed any more: its column takes dp/dc0
+      buf[n * TWP + LPB + l] = cmake<C>(dpdc(pv.x, Av.x, Bv.x, cc[i].x, aa[i].x),
+                                        dpdc(pv.y, Av.y, Bv.y, cc[i].y, aa[i].y));
   });
   __syncthreads();
+  if (want_hist) {
+    const int j0 = a.g.gam_off[l0], j1 = a.g.gam_off[l0 + nl];
+    T* hrow = a.hist + (size_t)si.step * a.d.n_gam;
+    for (int i = j0 + (int)threadIdx.x; i < j1; i += X_NT) {
+      const int l = local_line(a.g.gam_off, l0, nl, i);
+      hrow[i] = p_at<T, TWP>(buf, LPB, l, a.g.gam_x[i]);
+    }
+  }
   if (KIND == SP_SOURCE) {
     const int i0 = a.g.rec_off[l0], i1 = a.g.rec_off[l0 + nl];
     for (int i = i0 + (int)threadIdx.x; i < i1; i += X_NT) {

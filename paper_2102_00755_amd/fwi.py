@@ -185,12 +185,15 @@ class Handle:
                                      tr.data_ptr(), flags, self._stream()), "fwi_forward")
         return tr
 
-    def gradient(self, c, src_sig, w, obs, check=False, out=None, mean=False) -> Tuple[torch.Tensor, torch.Tensor]:
+    def gradient(self, c, src_sig, w, obs, check=False, out=None, mean=False,
+                 exact=False) -> Tuple[torch.Tensor, torch.Tensor]:
         """(misfit [B] float64, gradient [B, nz, ny, nx]) of the encoded TR gradient.
         check=True validates c against [c_min, c_max] and the result for
         finiteness (both read a device flag back, so the call synchronises).
         mean=True returns the mean of the B gradients as [1, nz, ny, nx]
-        (FWI_MEAN: averaged on the device in a fixed order)."""
+        (FWI_MEAN: averaged on the device in a fixed order).  exact=True
+        returns the exact discrete gradient instead (FWI_EXACT: reverse mode
+        over a stored dp/dc0 history on Gamma; B = 1)."""
         c = self._t(c, self.shape)
         B = c.shape[0]
         src = self._t(src_sig, (self.nt, self.n_src), batch=B)
@@ -207,6 +210,7 @@ class Handle:
         flags = (L.FWI_CHECK_INPUT | L.FWI_CHECK_FINITE if check else 0) | (L.FWI_GRAPH if self.use_graph else 0)
         flags |= L.FWI_TR_FINAL_STATE if self.tr_final_state else 0
         flags |= L.FWI_MEAN if mean else 0
+        flags |= L.FWI_EXACT if exact else 0
         self.tape_token += 1
         _check(self._lib.fwi_gradient(self._h, B, c.data_ptr(), src.data_ptr(), w.data_ptr(), obs.data_ptr(),
                                       mis.data_ptr(), grad.data_ptr(), flags, self._stream()), "fwi_gradient")
