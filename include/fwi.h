@@ -240,7 +240,8 @@ int fwi_set_tuning(fwi_handle* h, const fwi_tuning* t);
  * simulation switches the sign of tau when tr_flip != 0 (Sec. 3.1) and keeps
  * it otherwise; the gradient keeps the form of Alg. 1 (2 / c0^3 times the
  * second time difference of the TR pressure against the adjoint pressure,
- * without the dL/dc0 terms of App. A).
+ * without the dL/dc0 terms of App. A); fwi_gradient with FWI_EXACT returns
+ * the exact discrete gradient, which carries them.
  *   alpha0        Np (rad/s)^-y m^-1 (uniform), >= 0 and finite
  *   y             power-law exponent, 0 < y < 2, y != 1
  *   alpha0_field  NULL, or a device array [nz][ny][nx] of the handle's

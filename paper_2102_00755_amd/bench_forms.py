@@ -6,6 +6,7 @@
     python -m paper_2102_00755_amd.bench_forms multigrid
     python -m paper_2102_00755_amd.bench_forms lossy [--steps 2] [--nt 2200]
     python -m paper_2102_00755_amd.bench_forms latency [--steps 20]
+    python -m paper_2102_00755_amd.bench_forms exact [--nt 200]
 
 batched : 16 independent Rademacher-encoded TR gradients on 128^3 (phantom
           seeds 300..315, encoding seeds 1300..1315), run (a) one after
@@ -25,6 +26,8 @@ serve   : Poisson-arriving forward / gradient requests (50/50) over the grid
 lbfgs   : the SLBFGS two-loop recursion (64 pairs) and pair push at |Gamma| of
           the full workload, with their algorithmic bandwidth.
 multigrid: grid transfers between the 1 mm and 0.5 mm levels of the full box.
+exact   : the exact discrete gradient (FWI_EXACT) against the TR gradient on the
+          full workload (--nt, default 200 steps), without and with absorption.
 latency : p50 / p99 of repeated plain encoded TR gradients (one at a time, each
           synchronised): --steps solves of the full workload and 5x as many
           of the 128^3 workload.
@@ -322,6 +325,40 @@ def lossy(args) -> dict:
     return out
 
 
+def exact(args) -> dict:
+    """The exact discrete gradient (FWI_EXACT: stored dp/dc0 history on Gamma,
+    reverse sweep) against Alg. 1's TR gradient on the full workload, without
+    and with absorption (0.75 dB MHz^-1.5 cm^-1)."""
+    from synth import make_config
+    nt = args.nt or 200
+    prob = make_config("full", nt=nt)
+    h = fwi.Handle.from_problem(prob, precision=4)
+    dev = h.device
+    c_eval, c_true, S, w = (t.to(dev) for t in _gradient_inputs(prob, dev, torch.float32))
+    grad = torch.empty((1, *h.shape), device=dev, dtype=torch.float32)
+    out = {"form": "exact", "workload": "448x448x224, %d steps, 32 encoded emitters, 1024 receivers" % nt,
+           "history_GB": nt * int(prob.gamma.sum()) * 4 / 1e9}
+    for name, a_db in (("lossless", 0.0), ("lossy", 0.75)):
+        h.set_absorption(fwi.db_to_neper(a_db, 1.5), 1.5)
+        obs = h.forward(c_true, S, w)
+        res = {}
+        for kind, ex in (("tr", False), ("exact", True)):
+            h.gradient(c_eval, S, w, obs, out=grad, exact=ex)       # warm-up (allocates the history)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, g = h.gradient(c_eval, S, w, obs, exact=ex)
+            torch.cuda.synchronize()
+            res[kind + "_s"] = time.perf_counter() - t0
+            res[kind] = g.clone()
+        m = torch.from_numpy(prob.gamma.astype(bool)).to(dev)
+        d = (res["tr"][0][m].double() - res["exact"][0][m].double()).norm() / res["exact"][0][m].double().norm()
+        out[name] = {"tr_gradient_s": res["tr_s"], "exact_gradient_s": res["exact_s"],
+                     "exact_over_tr": res["exact_s"] / res["tr_s"], "tr_vs_exact_rel_l2": float(d)}
+        print(json.dumps({name: out[name]}), flush=True)
+    h.close()
+    return out
+
+
 def latency(args) -> dict:
     from synth import make_config
     out = {"form": "latency"}
@@ -352,7 +389,7 @@ def latency(args) -> dict:
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("form", choices=["batched", "serve", "lbfgs", "multigrid", "lossy", "latency"])
+    ap.add_argument("form", choices=["batched", "serve", "lbfgs", "multigrid", "lossy", "latency", "exact"])
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--nt", type=int, default=None)
@@ -366,7 +403,7 @@ def main():
     ap.add_argument("--m", type=int, default=64)
     args = ap.parse_args()
     res = {"batched": batched, "serve": serve, "lbfgs": lbfgs, "multigrid": multigrid,
-           "lossy": lossy, "latency": latency}[args.form](args)
+           "lossy": lossy, "latency": latency, "exact": exact}[args.form](args)
     print(json.dumps(res), flush=True)
 
 
