@@ -190,4 +190,11 @@ def test_autograd_backward_matches_finite_differences_at_128():
     # measured: 5.6 % (zero start) and 2.3 % (final-state start)
     assert err[True] < err[False]
     assert err[False] < 0.08 and err[True] < 0.04
+    # the exact discrete gradient (FWI_EXACT) is the derivative the central
+    # differences approximate: they agree to the differences' own O(h^2) error
+    h.tr_final_state = False
+    _, gex = h.gradient(base, S, w, obs, exact=True)
+    ex = gex[0].cpu().numpy()[tuple(pick.T)]
+    print(f"exact gradient vs central differences: {rel(ex, fd):.3e}", flush=True)
+    assert rel(ex, fd) < 1e-5
     h.close()
