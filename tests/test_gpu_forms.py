@@ -188,10 +188,11 @@ def test_tuning_is_bit_identical_and_autotune_caches(tmp_path):
             assert all(torch.equal(a, b) for a, b in zip(got, ref[plan])), tb
     # the two radix plans agree to FP32 rounding: traces to 1e-5; the misfit
     # and gradient, which depend on the small residual f(c_eval) - f(c_true)
-    # of two such traces, to the FP32 parity tolerance 1e-3
+    # of two such traces, to twice the FP32 parity tolerance (each plan is
+    # parity-tested against the oracle at 1e-3, so they may differ by 2e-3)
     assert float((ref[1][0] - ref[0][0]).norm() / ref[0][0].norm()) < 1e-5
-    assert abs(float(ref[1][1][0] - ref[0][1][0])) <= 1e-3 * abs(float(ref[0][1][0]))
-    assert float((ref[1][2] - ref[0][2]).norm() / ref[0][2].norm()) < 1e-3
+    assert abs(float(ref[1][1][0] - ref[0][1][0])) <= 2e-3 * abs(float(ref[0][1][0]))
+    assert float((ref[1][2] - ref[0][2]).norm() / ref[0][2].norm()) < 2e-3
     with pytest.raises(FwiError):
         h.tuning = {"y_tile_bytes": 96}
     with pytest.raises(FwiError):
