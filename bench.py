@@ -26,9 +26,9 @@ if ROOT not in sys.path:
 
 METRIC = "Mcell-steps/s of TR-gradient at 448x448x224 FP32; p50/p99 solve latency"
 PEAK_HBM_GBS = 8000.0
-# algorithmic HBM bytes per cell and simulation step of the nine-pass step
-# (43 field-sized reads and writes of 4 bytes; the pass table of the kernels)
-STEP_BYTES_PER_CELL = 172.0
+# algorithmic HBM bytes per cell and simulation step of the eight-pass step
+# (40 field-sized reads and writes of 4 bytes; the pass table of the kernels)
+STEP_BYTES_PER_CELL = 160.0
 
 KERNEL_SYMBOLS = {
     "y_fwd": "k_axis_y<float, {ny}, false, {ty}, {py}>",
@@ -38,8 +38,7 @@ KERNEL_SYMBOLS = {
     "x_vel": "k_x_velocity<float, {m}, {px}>",
     "x_den_fwd": "k_x_density<float, {m}, 0, {px}>",
     "x_den_pair": "k_x_density<float, {m}, 1, {px}>",
-    "y_vel_q": "k_axis_y_vel<float, {ny}, {ty}, 0, {py}>",
-    "y_vel_r": "k_axis_y_vel<float, {ny}, {ty}, 1, {py}>",
+    "y_vel_q": "k_axis_y_vel<float, {ny}, {ty}, {py}>",
 }
 
 

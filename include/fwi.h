@@ -263,14 +263,13 @@ int fwi_set_absorption(fwi_handle* h, double alpha0, double y, const void* alpha
 enum {
   FWI_PASS_Y_FWD = 0,    /* forward y-FFT                                     */
   FWI_PASS_Y_INV = 1,    /* inverse y-FFT                                     */
-  FWI_PASS_Z_PLUS = 2,   /* z-FFT, k-space multiply for d+ (1 -> 2 fields)    */
+  FWI_PASS_Z_PLUS = 2,   /* z-FFT, k-space multiply for d+, v_z update        */
   FWI_PASS_Z_MINUS = 3,  /* z-FFT, k-space multiply for d- (3 -> 3 fields)    */
   FWI_PASS_X_VEL = 4,    /* C2R, v_x update, R2C                              */
   FWI_PASS_X_DEN_FWD = 5,  /* C2R, density/EOS/sources/sensors/tape, R2C       */
   FWI_PASS_X_DEN_PAIR = 6, /* adjoint + TR density passes with gradient        */
   FWI_PASS_Y_VEL_Q = 7,  /* inverse y-FFT of Q (Z2) with the v_y update        */
-  FWI_PASS_Y_VEL_R = 8,  /* inverse y-FFT of R (Z2) with the v_z update        */
-  FWI_PASS_COUNT = 9
+  FWI_PASS_COUNT = 8
 };
 
 /* Sampled timing of the pass launches, for roofline measurement: when

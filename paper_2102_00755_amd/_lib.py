@@ -48,10 +48,9 @@ EXPORTED = (
     "fwi_status_string", "fwi_last_error",
 )
 
-PASS_NAMES = ("y_fwd", "y_inv", "z_plus", "z_minus", "x_vel", "x_den_fwd", "x_den_pair", "y_vel_q", "y_vel_r")
+PASS_NAMES = ("y_fwd", "y_inv", "z_plus", "z_minus", "x_vel", "x_den_fwd", "x_den_pair", "y_vel_q")
 PASS_KERNELS = ("k_axis_y<*, false, *>", "k_axis_y<*, true, *>", "k_axis_z_plus", "k_axis_z_minus",
-                "k_x_velocity", "k_x_density<*, 0, *>", "k_x_density<*, 1, *>", "k_axis_y_vel<*, 0, *>",
-                "k_axis_y_vel<*, 1, *>")
+                "k_x_velocity", "k_x_density<*, 0, *>", "k_x_density<*, 1, *>", "k_axis_y_vel")
 
 
 class FwiLibraryMissing(ImportError):

@@ -40,7 +40,7 @@ from . import fwi
 TILE_BYTES = (64, 128)
 # pass kinds of the per-pass timer that each tuning field governs
 KIND_PASSES = {
-    "y_tile_bytes": ("y_fwd", "y_inv", "y_vel_q", "y_vel_r"),
+    "y_tile_bytes": ("y_fwd", "y_inv", "y_vel_q"),
     "zm_tile_bytes": ("z_minus",),
     "zp_tile_bytes": ("z_plus",),
 }

@@ -34,7 +34,7 @@ hipError_t launch_axis_zp(int L, int tb, int plan, dim3 grid, hipStream_t st, co
 template <typename T>
 hipError_t launch_axis_ys(int L, int tb, int plan, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
 template <typename T>
-hipError_t launch_axis_yv(int L, int part, int tb, int plan, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
+hipError_t launch_axis_yv(int L, int tb, int plan, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
 // absorption z pass (k_axis_z_frac)
 template <typename T>
 hipError_t launch_axis_zf(int L, int tb, int plan, dim3 grid, hipStream_t st, const AxisArgs<T>& a);

@@ -561,6 +561,7 @@ template <typename T> struct Engine : EngineBase {
     a.vcoef = (T)((double)p.nx * p.dt / p.rho0);
     a.half_e0 = (T)((ypow - 1.0) / 2.0);
     a.half_e1 = (T)((ypow - 2.0) / 2.0);
+    a.vz_state = 0;
     return a;
   }
   // tiles per spectrum row of an axis pass of kind k (AxisKind)
@@ -573,8 +574,8 @@ template <typename T> struct Engine : EngineBase {
   double sbytes() const { return (double)(d.M + 1) * d.ny * d.nz * sizeof(C); }
   double fbytes() const { return (double)d.nfield * sizeof(T); }
 
-  // Y3 .. Y2 of one step (seven passes; X2 follows); half_only stops after the
-  // velocity passes (Y4 with v_y, v_z and X1 with v_x)
+  // Y3 .. Y2 of one step (six passes; X2 follows); half_only stops after the
+  // velocity passes (Z2 with v_z, Y4 with v_y, X1 with v_x)
   int step_spectral(int slot0, int na, int slot1, int nslots, hipStream_t st, bool half_only = false) {
     const int ty = tile_bytes[AK_Y], tzm = tile_bytes[AK_ZMINUS], tzp = tile_bytes[AK_ZPLUS];
     const dim3 gy(ntx(AK_Y) * d.nz, nslots * 1), gy3(ntx(AK_Y) * d.nz, nslots * 3);
@@ -585,14 +586,13 @@ template <typename T> struct Engine : EngineBase {
     FWI_HIP(launch_axis_y<T>(d.ny, false, ty, plans[AK_Y], gy, st, axis_args(slot0, na, slot1, 1, 0)));   // Y3
     timer.end(ev, FWI_PASS_Y_FWD, 2 * ns * S, st);
     ev = timer.begin(st);
-    FWI_HIP(launch_axis_zp<T>(d.nz, tzp, plans[AK_ZPLUS], gz, st, axis_args(slot0, na, slot1, 1, 0)));        // Z2
-    timer.end(ev, FWI_PASS_Z_PLUS, 3 * ns * S, st);
+    AxisArgs<T> az = axis_args(slot0, na, slot1, 1, 0);
+    az.vz_state = 1;
+    FWI_HIP(launch_axis_zp<T>(d.nz, tzp, plans[AK_ZPLUS], gz, st, az));        // Z2: Q, v_z
+    timer.end(ev, FWI_PASS_Z_PLUS, 4 * ns * S, st);
     ev = timer.begin(st);
-    FWI_HIP(launch_axis_yv<T>(d.ny, 0, ty, plans[AK_Y], gy, st, axis_args(slot0, na, slot1, 1, 0)));    // Y4: Q, v_y
+    FWI_HIP(launch_axis_yv<T>(d.ny, ty, plans[AK_Y], gy, st, axis_args(slot0, na, slot1, 1, 0)));    // Y4: Q, v_y
     timer.end(ev, FWI_PASS_Y_VEL_Q, 5 * ns * S, st);
-    ev = timer.begin(st);
-    FWI_HIP(launch_axis_yv<T>(d.ny, 1, ty, plans[AK_Y], gy, st, axis_args(slot0, na, slot1, 1, 0)));    // Y4: R, v_z
-    timer.end(ev, FWI_PASS_Y_VEL_R, 4 * ns * S, st);
     XArgs<T> xa;
     xa.slots = slot_table; xa.slot0 = slot0; xa.na = na; xa.slot1 = slot1;
     xa.d = d; xa.tb = tb; xa.dt_rho = (T)(p.dt / p.rho0);
@@ -605,7 +605,9 @@ template <typename T> struct Engine : EngineBase {
     FWI_HIP(launch_axis_y<T>(d.ny, false, ty, plans[AK_Y], gy, st, axis_args(slot0, na, slot1, 1, 0)));   // Y1 (v_x)
     timer.end(ev, FWI_PASS_Y_FWD, 2 * ns * S, st);
     ev = timer.begin(st);
-    FWI_HIP(launch_axis_zm<T>(d.nz, tzm, plans[AK_ZMINUS], gz3, st, axis_args(slot0, na, slot1, 3, 0)));       // Z1
+    AxisArgs<T> a1 = axis_args(slot0, na, slot1, 3, 0);
+    a1.vz_state = 1;
+    FWI_HIP(launch_axis_zm<T>(d.nz, tzm, plans[AK_ZMINUS], gz3, st, a1));       // Z1
     timer.end(ev, FWI_PASS_Z_MINUS, 6 * ns * S, st);
     ev = timer.begin(st);
     FWI_HIP(launch_axis_y<T>(d.ny, true, ty, plans[AK_Y], gy3, st, axis_args(slot0, na, slot1, 3, 0)));   // Y2

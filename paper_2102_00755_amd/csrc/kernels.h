@@ -1,18 +1,18 @@
 // HIP kernels of one k-space time step (App. B) and of the TR gradient
 // (Alg. 1), written for gfx950.
 //
-// One time step of one simulation is nine launches, each one HBM pass:
+// One time step of one simulation is eight launches, each one HBM pass:
 //   Y3  forward y-FFT of p_hat                       (1 field in place)
 //   Z2  forward z-FFT, x kappa (Q) and x kappa i k_z e^{+i k_z dz/2} (R),
-//       inverse z-FFT                                 (1 field -> 2 fields)
+//       inverse z-FFT; Q is stored, R advances v_z, which is kept as its
+//       x-y spectrum W_z (its PML factor depends on z alone)
 //   Y4q inverse y-FFT of Q; the same after x i k_y e^{+i k_y dy/2}, which
 //       advances the x spectrum of v_y, then its forward y-FFT
-//   Y4r inverse y-FFT of R, which advances the x spectrum of v_z, then its
-//       forward y-FFT
 //   X1  x i k_x e^{+i k_x dx/2}, inverse x (C2R) -> d+_x p, v_x update with
 //       PML, forward x (R2C)
 //   Y1  forward y-FFT of the x spectrum of v_x        (1 field)
 //   Z1  forward z-FFT, x kappa * i k_a e^{-i k_a dx/2}, inverse z-FFT
+//       (v_z: read from W_z, which it leaves in place)
 //   Y2  inverse y-FFT                                 (3 fields)
 //   X2  inverse x (C2R) -> d-_a v_a, split-density update with PML, source /
 //       adjoint injection or Dirichlet imposition, equation of state, sensor
@@ -157,6 +157,8 @@ template <typename T> struct AxisArgs {
   T vcoef;     // nx dt / rho0: velocity update of the x-spectrum states
   T half_e0;   // absorption pass: |k|^{2 half_e0} on field 0 (B[s]: (y - 1) / 2)
   T half_e1;   //                  |k|^{2 half_e1} on field 1 (A[d]: (y - 2) / 2)
+  int vz_state;  // time step: Z2 advances W_z (slot v[2]) with R instead of
+                 // storing R, and Z1 reads field 2 from W_z
 };
 
 __device__ __forceinline__ int slot_of(int i, int slot0, int na, int slot1) {
@@ -360,14 +362,16 @@ k_axis_z_minus(AxisArgs<T> a) {
   const int f = a.f0 + blockIdx.y % a.nf;
   const size_t px = a.d.px;
   const size_t rstride = (size_t)a.d.ny * px;
-  C* g = a.slots[s].spec[f] + (size_t)y * px + (size_t)tile * TW;
+  const size_t off = (size_t)y * px + (size_t)tile * TW;
+  C* g = a.slots[s].spec[f] + off;
+  const C* gin = (a.vz_state && f == 2) ? reinterpret_cast<const C*>(a.slots[s].v[2]) + off : g;
   const int ncol = min(TW, (int)px - tile * TW);
   const int kx = min(tile * TW + (int)threadIdx.x % TW, a.d.M);
   T kap[EPT];
   C m[EPT];
   z_kappa<T, L, TW, NT>(a, kx, y, kap);
   z_mult<T, L, TW, NT>(a, a.tb.sfac_m, f, kx, y, kap, m);
-  tile_load<T, L, TW, NT>(buf, g, rstride, ncol, twl, a.tb.tw_z);
+  tile_load<T, L, TW, NT>(buf, gin, rstride, ncol, twl, a.tb.tw_z);
   __syncthreads();
   lds_fft<T, L, TW, TW, NT, false, PL>(buf, twl);
   z_apply<T, L, TW, NT>(buf, m, nullptr);
@@ -382,6 +386,13 @@ k_axis_z_minus(AxisArgs<T> a) {
 // The shift factors i k_a e^{+i k_a da/2} of x and y are separable and are
 // applied later, in the y pass (y) and the x pass (x), where those wave
 // numbers are at hand: one spectrum less is written here and read there.
+// In the time step (vz_state) R is not stored: it advances v_z at once.
+// v_z is kept as W_z = F_y F_x v_z (z in real space); its PML factor
+// Lambda^s_z(z) is constant in x and y, so the momentum step
+// v_z <- L_z (L_z v_z - dt/rho0 d+_z p) commutes with F_y F_x, and with
+// F_y F_x d+_z p = nx ny R (R being the y-x spectrum of d+_z p / (nx ny),
+// since the normalisation is folded into kappa) it reads
+//   W_z <- L_z (L_z W_z - ny vcoef R),  vcoef = nx dt / rho0.
 // L == nz.
 template <typename T, int L, int TB, int PL = 0>
 __global__ void __launch_bounds__(axis_nt(L, tile_tw<T, TB>()))
@@ -430,7 +441,26 @@ k_axis_z_plus(AxisArgs<T> a) {
   z_apply<T, L, TW, NT>(buf, m, xr);
   __syncthreads();
   lds_fft<T, L, TW, TW, NT, true, PL>(buf, twl);
-  tile_store<T, L, TW, NT>(buf, s2 + off, rstride, ncol);
+  if (!a.vz_state) {
+    tile_store<T, L, TW, NT>(buf, s2 + off, rstride, ncol);
+    return;
+  }
+  C* const gw = reinterpret_cast<C*>(a.slots[s].v[2]) + off;
+  C w[EPT];
+  T lz[EPT];
+  tile_prefetch<T, L, TW, NT>(w, gw, rstride, ncol);
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) lz[i] = gld(a.tb.pml_s[2] + min(((int)threadIdx.x + i * NT) / TW, L - 1));
+  const T cf = a.vcoef * (T)a.d.ny;
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = (int)threadIdx.x + i * NT;
+    if (((L * TW) % NT == 0 || e < L * TW) && e % TW < ncol) {
+      const C r = buf[e];
+      const C wn = cmake<C>(lz[i] * (lz[i] * w[i].x - cf * r.x), lz[i] * (lz[i] * w[i].y - cf * r.y));
+      gst(gw + (size_t)(e / TW) * rstride + e % TW, wn);
+    }
+  }
 }
 
 // x^e for normal x > 0 in the kernel's precision.  FP32: 2^(e log2 x) with
@@ -545,39 +575,34 @@ k_axis_y_split(AxisArgs<T> a) {
 }
 
 // Inverse y pass of the time step, fused with the velocity update of v_y and
-// v_z and with their forward y transforms.  v_y and v_z are kept as x
-// spectra V_a = F_x v_a (unnormalised R2C, rows of px complex): their PML
-// factor Lambda^s_a depends on y (a = y) or on z (a = z) only, i.e. it is a
-// constant along every x-line, so v_a <- L_a (L_a v_a - dt/rho0 d+_a p)
-// (Alg. 1 momentum step) commutes with F_x and is applied here, where
-// F_x d+_a p is at hand; the velocity x pass then handles v_x only.  Per slot
-// (grid.y = slots), one launch per part:
-//   part 0: Q (field 0) -> F_y^-1 Q to field 0 (d+_x p, finished by X1);
-//           G = F_y^-1 (i k_y e^{+i k_y dy/2} Q) = F_x(d+_y p) / nx;
-//           V_y <- L_y (L_y V_y - nx dt/rho0 G);  F_y V_y -> field 1
-//   part 1: R (field 2): G = F_y^-1 R = F_x(d+_z p) / nx;
-//           V_z <- L_z (L_z V_z - nx dt/rho0 G);  F_y V_z -> field 2
-// The two parts are separate kernels so that each gets its own register
-// allocation.  L == ny.
-// LATE: the velocity state is loaded after the inverse transform (not held
-// in registers through it), else vs_in holds it, prefetched by the caller.
-template <typename T, int L, int TW, int NT, int PL, bool LATE>
-__device__ __forceinline__ void y_vel_update(cplx<T>* buf, const cplx<T>* twl, const cplx<T>* vs_in,
-                                             const T* lam_row, T lam_all, T vcoef, cplx<T>* gv, cplx<T>* gout,
-                                             size_t px, int ncol) {
+// its forward y transform.  v_y is kept as its x spectrum V_y = F_x v_y
+// (unnormalised R2C, rows of px complex): its PML factor Lambda^s_y depends
+// on y only, i.e. it is a constant along every x-line, so
+// v_y <- L_y (L_y v_y - dt/rho0 d+_y p) (Alg. 1 momentum step) commutes with
+// F_x and is applied here, where F_x d+_y p is at hand.  Per slot (grid.y =
+// slots): Q (field 0) -> F_y^-1 Q to field 0 (d+_x p, finished by X1);
+//   G = F_y^-1 (i k_y e^{+i k_y dy/2} Q) = F_x(d+_y p) / nx;
+//   V_y <- L_y (L_y V_y - nx dt/rho0 G);  F_y V_y -> field 1.
+// (v_z, whose factor depends on z, is advanced in the Z2 pass; v_x in X1.)
+// L == ny.
+// Inverse transform of the tile in LDS (G), V <- lam (lam V - vcoef G) on the
+// state rows of gv (loaded only now, so that no tile is held in registers
+// through the transform), then the forward transform of V to gout.
+template <typename T, int L, int TW, int NT, int PL>
+__device__ __forceinline__ void y_vel_update(cplx<T>* buf, const cplx<T>* twl, const T* lam_row, T vcoef, cplx<T>* gv,
+                                             cplx<T>* gout, size_t px, int ncol) {
   using C = cplx<T>;
   constexpr int E = L * TW;
   constexpr int EPT = (E + NT - 1) / NT;
   lds_fft<T, L, TW, TW, NT, true, PL>(buf, twl);
-  C vs_late[LATE ? EPT : 1];
-  if constexpr (LATE) tile_prefetch<T, L, TW, NT>(vs_late, gv, px, ncol);
-  const C* vs = LATE ? vs_late : vs_in;
+  C vs[EPT];
+  tile_prefetch<T, L, TW, NT>(vs, gv, px, ncol);
   // each thread updates the elements it loaded (same element map as the tile load)
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int e = (int)threadIdx.x + i * NT;
     if (E % NT == 0 || e < E) {
-      const T lam = lam_row ? lam_row[e / TW] : lam_all;
+      const T lam = lam_row[e / TW];
       const C g = buf[e];
       const C vn = cmake<C>(lam * (lam * vs[i].x - vcoef * g.x), lam * (lam * vs[i].y - vcoef * g.y));
       buf[e] = vn;
@@ -589,7 +614,7 @@ __device__ __forceinline__ void y_vel_update(cplx<T>* buf, const cplx<T>* twl, c
   tile_store<T, L, TW, NT>(buf, gout, px, ncol);
 }
 
-// Waves per SIMD the velocity y passes are compiled for: 4 (two workgroups of
+// Waves per SIMD the velocity y pass is compiled for: 4 (two workgroups of
 // 8 waves per CU) in FP32 where a thread holds at most 14 tile elements, else
 // the compiler's choice (FP64 would spill)
 template <typename T, int L, int TB> constexpr int yv_waves() {
@@ -598,7 +623,7 @@ template <typename T, int L, int TB> constexpr int yv_waves() {
              ? 4
              : 1;
 }
-template <typename T, int L, int TB, int PART, int PL = 0>
+template <typename T, int L, int TB, int PL = 0>
 __global__ void __launch_bounds__(axis_nt(L, tile_tw<T, TB>()))
 __attribute__((amdgpu_waves_per_eu(yv_waves<T, L, TB>()))) k_axis_y_vel(AxisArgs<T> a) {
   using C = cplx<T>;
@@ -609,8 +634,8 @@ __attribute__((amdgpu_waves_per_eu(yv_waves<T, L, TB>()))) k_axis_y_vel(AxisArgs
   constexpr int TPT = TwRegs<L, NT>::N_PER;
   __shared__ C buf[L * TW];
   __shared__ C twl[L];
-  __shared__ C sfl[L];   // part 0: i k_y e^{+i k_y dy/2}
-  __shared__ T lml[L];   // part 0: Lambda^s_y
+  __shared__ C sfl[L];   // i k_y e^{+i k_y dy/2}
+  __shared__ T lml[L];   // Lambda^s_y
   const int ntx = (a.d.px + TW - 1) / TW;   // tiles per spectrum row
   const int tl = tile_linear<TB>();
   const int tile = tl % ntx;
@@ -619,61 +644,44 @@ __attribute__((amdgpu_waves_per_eu(yv_waves<T, L, TB>()))) k_axis_y_vel(AxisArgs
   const size_t px = a.d.px;
   const size_t off = (size_t)z * L * px + (size_t)tile * TW;
   const int ncol = min(TW, (int)px - tile * TW);
-  if constexpr (PART == 0) {
-    C* const gq = sl.spec[0] + off;
-    C q[EPT];
-    {
-      C tt[TPT], ts[TPT];
-      T tl[TPT];
-      tile_prefetch<T, L, TW, NT>(q, gq, px, ncol);
-      tw_prefetch<T, L, NT>(tt, a.tb.tw_y);
-      tw_prefetch<T, L, NT>(ts, a.tb.sfac_p[1]);
+  C* const gq = sl.spec[0] + off;
+  C q[EPT];
+  {
+    C tt[TPT], ts[TPT];
+    T tl[TPT];
+    tile_prefetch<T, L, TW, NT>(q, gq, px, ncol);
+    tw_prefetch<T, L, NT>(tt, a.tb.tw_y);
+    tw_prefetch<T, L, NT>(ts, a.tb.sfac_p[1]);
 #pragma unroll
-      for (int i = 0; i < TPT; ++i) tl[i] = gld(a.tb.pml_s[1] + min((int)threadIdx.x + i * NT, L - 1));
-      tile_commit<T, L, TW, NT>(buf, q);
-      tw_commit<T, L, NT>(twl, tt);
-      tw_commit<T, L, NT>(sfl, ts);
+    for (int i = 0; i < TPT; ++i) tl[i] = gld(a.tb.pml_s[1] + min((int)threadIdx.x + i * NT, L - 1));
+    tile_commit<T, L, TW, NT>(buf, q);
+    tw_commit<T, L, NT>(twl, tt);
+    tw_commit<T, L, NT>(sfl, ts);
 #pragma unroll
-      for (int i = 0; i < TPT; ++i) {
-        const int e = (int)threadIdx.x + i * NT;
-        if (L % NT == 0 || e < L) lml[e] = tl[i];
-      }
-    }
-    __syncthreads();
-    lds_fft<T, L, TW, TW, NT, true, PL>(buf, twl);
-    tile_store<T, L, TW, NT>(buf, gq, px, ncol);     // F_y^-1 Q
-    __syncthreads();
-    // Q again from F_y^-1 Q (a forward transform in LDS gives L Q) instead of
-    // keeping the loaded tile in registers through the first transform: with
-    // the velocity state loaded only after the next transform, the kernel
-    // fits 128 VGPRs, two 448-row groups run per CU, and the pass takes 11 %
-    // less time (448x448x224 FP32)
-    lds_fft<T, L, TW, TW, NT, false, PL>(buf, twl);
-    const T inv_l = (T)1 / (T)L;
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
+    for (int i = 0; i < TPT; ++i) {
       const int e = (int)threadIdx.x + i * NT;
-      if (E % NT == 0 || e < E) buf[e] = cscale(cmul(sfl[e / TW], buf[e]), inv_l);
+      if (L % NT == 0 || e < L) lml[e] = tl[i];
     }
-    C* const gv = reinterpret_cast<C*>(sl.v[1]) + off;
-    __syncthreads();
-    y_vel_update<T, L, TW, NT, PL, true>(buf, twl, nullptr, lml, (T)1, a.vcoef, gv, sl.spec[1] + off, px, ncol);
-  } else {
-    C* const gr = sl.spec[2] + off;
-    C* const gv = reinterpret_cast<C*>(sl.v[2]) + off;
-    C vs[EPT];
-    {
-      C tmp[EPT], tt[TPT];
-      tile_prefetch<T, L, TW, NT>(tmp, gr, px, ncol);
-      tile_prefetch<T, L, TW, NT>(vs, gv, px, ncol);
-      tw_prefetch<T, L, NT>(tt, a.tb.tw_y);
-      tile_commit<T, L, TW, NT>(buf, tmp);
-      tw_commit<T, L, NT>(twl, tt);
-    }
-    const T lz = gld(a.tb.pml_s[2] + z);
-    __syncthreads();
-    y_vel_update<T, L, TW, NT, PL, false>(buf, twl, vs, nullptr, lz, a.vcoef, gv, gr, px, ncol);
   }
+  __syncthreads();
+  lds_fft<T, L, TW, TW, NT, true, PL>(buf, twl);
+  tile_store<T, L, TW, NT>(buf, gq, px, ncol);     // F_y^-1 Q
+  __syncthreads();
+  // Q again from F_y^-1 Q (a forward transform in LDS gives L Q) instead of
+  // keeping the loaded tile in registers through the first transform: with
+  // the velocity state loaded only after the next transform, the kernel
+  // fits 128 VGPRs, two 448-row groups run per CU, and the pass takes 11 %
+  // less time (448x448x224 FP32)
+  lds_fft<T, L, TW, TW, NT, false, PL>(buf, twl);
+  const T inv_l = (T)1 / (T)L;
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = (int)threadIdx.x + i * NT;
+    if (E % NT == 0 || e < E) buf[e] = cscale(cmul(sfl[e / TW], buf[e]), inv_l);
+  }
+  C* const gv = reinterpret_cast<C*>(sl.v[1]) + off;
+  __syncthreads();
+  y_vel_update<T, L, TW, NT, PL>(buf, twl, lml, a.vcoef, gv, sl.spec[1] + off, px, ncol);
 }
 
 // ----------------------------------------------------------------------------
