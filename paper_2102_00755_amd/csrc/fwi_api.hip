@@ -573,6 +573,18 @@ template <typename T> struct Engine : EngineBase {
   // algorithmic bytes of one half spectrum / one real field
   double sbytes() const { return (double)(d.M + 1) * d.ny * d.nz * sizeof(C); }
   double fbytes() const { return (double)d.nfield * sizeof(T); }
+  // split-density reads + writes of one density step, in fields: 6 on the
+  // lines in a y or z PML slab, 2 plus rho_x on the x-PML pairs elsewhere
+  // (the storage of density_update)
+  double rho_fields() const {
+    auto in = [](int i, int n, int P) { return i < P || i > n - 1 - P; };
+    long long full = 0, xp = 0;
+    for (int z = 0; z < d.nz; ++z)
+      for (int y = 0; y < d.ny; ++y) full += (in(y, d.ny, p.pml[1]) || in(z, d.nz, p.pml[2])) ? 1 : 0;
+    for (int n = 0; n < d.M; ++n) xp += (in(2 * n, d.nx, p.pml[0]) || in(2 * n + 1, d.nx, p.pml[0])) ? 1 : 0;
+    const double acc = 6.0 * d.nx * full + (2.0 * d.nx + 4.0 * xp) * (double)(d.nlines - full);
+    return acc / ((double)d.nlines * d.nx);
+  }
 
   // Y3 .. Y2 of one step (six passes; X2 follows); half_only stops after the
   // velocity passes (Z2 with v_z, Y4 with v_y, X1 with v_x)
@@ -625,6 +637,7 @@ template <typename T> struct Engine : EngineBase {
     a.ring = ring; a.gacc = gacc;
     a.delay = delays_on ? delay : nullptr;
     a.hist = hist_ptr;
+    for (int k = 0; k < 3; ++k) a.pml[k] = p.pml[k];
     return a;
   }
   int launch_x2(int mode, int B, const X2Args<T>& a, hipStream_t st) {
@@ -634,12 +647,12 @@ template <typename T> struct Engine : EngineBase {
     FWI_HIP(launch_x_den<T>(d.M, mode, x_plan, dim3((d.nlines + lpb - 1) / lpb, B), st, a));
     if (mode == XM_FWD) {
       // 3 spectra in, 1 out, split densities r/w, c0, source row, trace row, tape row
-      const double b = B * (4 * S + 7 * F + t * (d.n_src + d.n_rec + (a.tape ? d.n_bnd : 0)));
+      const double b = B * (4 * S + (1 + rho_fields()) * F + t * (d.n_src + d.n_rec + (a.tape ? d.n_bnd : 0)));
       timer.end(ev, FWI_PASS_X_DEN_FWD, b, st);
     } else if (mode == XM_PAIR) {
-      // two simulations of (4 S + 6 F), c0 once, adjoint source row, tape row,
-      // ring (2 reads + 1 write), FP64 accumulator read + write
-      const double b = B * (2 * (4 * S + 6 * F) + F + t * (d.n_rec + d.n_bnd + 3.0 * d.n_gam) + 16.0 * d.n_gam);
+      // two simulations of (4 S + split densities), c0 once, adjoint source
+      // row, tape row, ring (2 reads + 1 write), FP64 accumulator read + write
+      const double b = B * (2 * (4 * S + rho_fields() * F) + F + t * (d.n_rec + d.n_bnd + 3.0 * d.n_gam) + 16.0 * d.n_gam);
       timer.end(ev, FWI_PASS_X_DEN_PAIR, b, st);
     }
     return FWI_OK;

@@ -975,7 +975,27 @@ template <typename T> struct X2Args {
   // exact gradient: [nt][n_gam] dp/dc0 at fixed state on Gamma per forward
   // step (problem 0), or null
   T* hist;
+  int pml[3];            // PML cells at both ends of x, y, z (normal grid: Lambda != 1 there)
 };
+
+// Storage of the split densities (three real fields per slot).  Inside the
+// PML of axis a the component rho_a is damped by Lambda_a and must be kept
+// apart; elsewhere the components evolve alike (rho_a <- rho_a - dt rho0
+// d-_a v_a) and only their sum enters the equation of state.  So an x-line
+// outside the y and z PML slabs (most lines) keeps in field 0 the undamped
+// part u = sum of the components with Lambda_a = 1 (all three, or rho_y +
+// rho_z on the x-PML voxels), and in field 1 rho_x on the x-PML voxels only;
+// field 2 is not used there.  Lines in a y or z slab keep the three
+// components.  Same arithmetic, 2 + 4 P_x / nx instead of 6 field accesses
+// per voxel on those lines.
+__device__ __forceinline__ bool in_pml(int i, int n, int P) { return i < P || i > n - 1 - P; }
+template <typename T> __device__ __forceinline__ bool full_split_line(const X2Args<T>& a, int line) {
+  return in_pml(line % a.d.ny, a.d.ny, a.pml[1]) || in_pml(line / a.d.ny, a.d.nz, a.pml[2]);
+}
+// the voxel pair (2n, 2n+1) of an x-line touches the x PML
+template <typename T> __device__ __forceinline__ bool x_pml_pair(const X2Args<T>& a, int n) {
+  return in_pml(2 * n, a.d.nx, a.pml[0]) || in_pml(2 * n + 1, a.d.nx, a.pml[0]);
+}
 
 // Per-launch step indices of an X2 launch.
 struct StepIdx {
@@ -1045,8 +1065,10 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx
     const size_t lo = (size_t)line * nx;
     if (!LOSSY) cc[i] = gld(reinterpret_cast<const C*>(cb + lo) + n);
     if (!zero_state) {
-#pragma unroll
-      for (int f = 0; f < 3; ++f) rr[i][f] = gld(reinterpret_cast<const C*>(sl.rho[f] + lo) + n);
+      const bool full = full_split_line(a, line);
+      rr[i][0] = gld(reinterpret_cast<const C*>(sl.rho[0] + lo) + n);
+      rr[i][1] = (full || x_pml_pair(a, n)) ? gld(reinterpret_cast<const C*>(sl.rho[1] + lo) + n) : cmake<C>((T)0, (T)0);
+      rr[i][2] = full ? gld(reinterpret_cast<const C*>(sl.rho[2] + lo) + n) : cmake<C>((T)0, (T)0);
     }
     if (!no_step) {
       l0f[i] = gld(reinterpret_cast<const C*>(a.tb.pml_n[0]) + n);
@@ -1117,6 +1139,38 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx
     const C sv = spv[n * LPB + l];
     C sum = cmake<C>((T)0, (T)0);
     C dsum = cmake<C>((T)0, (T)0);
+    if (!full_split_line(a, line)) {
+      // undamped part u in field 0, rho_x on the x-PML pairs in field 1
+      const bool xp = x_pml_pair(a, n);
+      const T nu = xp ? (T)2 : (T)3;   // components in u
+      C u, rx = cmake<C>((T)0, (T)0);
+      if (zero_state) {
+        u = cmake<C>((T)0, (T)0);
+      } else if (no_step) {
+        u = rr[i][0];
+        rx = rr[i][1];
+      } else {
+        const C d0 = buf[n * TWP + l], d1 = buf[n * TWP + LPB + l], d2 = buf[n * TWP + 2 * LPB + l];
+        if (LOSSY) dsum = cadd(cadd(d0, d1), d2);
+        const C du = xp ? cadd(d1, d2) : cadd(cadd(d0, d1), d2);
+        u = cmake<C>(rr[i][0].x - a.dt_rho0 * du.x, rr[i][0].y - a.dt_rho0 * du.y);
+        if (xp) {
+          const T lx = l0f[i].x, ly = l0f[i].y;
+          rx = cmake<C>(lx * (lx * rr[i][1].x - a.dt_rho0 * d0.x), ly * (ly * rr[i][1].y - a.dt_rho0 * d0.y));
+        }
+      }
+      if (KIND == SP_DIRICHLET) {
+        if (spm[2 * (n * LPB + l)]) { u.x = nu * sv.x; rx.x = sv.x; }
+        if (spm[2 * (n * LPB + l) + 1]) { u.y = nu * sv.y; rx.y = sv.y; }
+      } else {
+        u = cmake<C>(u.x + nu * sv.x, u.y + nu * sv.y);
+        rx = cadd(rx, sv);
+      }
+      const size_t lo = (size_t)line * nx;
+      gst(reinterpret_cast<C*>(sl.rho[0] + lo) + n, u);
+      if (xp) gst(reinterpret_cast<C*>(sl.rho[1] + lo) + n, rx);
+      sum = xp ? cadd(u, rx) : u;
+    } else
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
       C* rp = reinterpret_cast<C*>(sl.rho[f] + (size_t)line * nx) + n;
