@@ -52,6 +52,7 @@ hipError_t launch_x_c2r(int M, dim3 grid, hipStream_t st, const XArgs<T>& a, T* 
 template <typename T> inline int x_lines_per_block(int M) { return x_lpb<T>(M); }
 template <typename T> inline int x_lines_per_block_vel(int M) { return x_lpb_vel<T>(M); }
 template <typename T> inline int x_lines_per_block_den(int M) { return x_lpb_den<T>(M); }
+template <typename T> inline int x_lines_per_block_den(int M, int mode) { return x_lpb_den_mode<T>(M, mode); }
 template <typename T> inline int x_lines_per_block_eos(int M) { return x_lpb_eos<T>(M); }
 
 }  // namespace fwi

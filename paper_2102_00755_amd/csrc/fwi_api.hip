@@ -641,7 +641,7 @@ template <typename T> struct Engine : EngineBase {
     return a;
   }
   int launch_x2(int mode, int B, const X2Args<T>& a, hipStream_t st) {
-    const int lpb = x_lines_per_block_den<T>(d.M);
+    const int lpb = x_lines_per_block_den<T>(d.M, mode);
     const double S = sbytes(), F = fbytes(), t = sizeof(T);
     hipEvent_t ev = (mode == XM_FWD || mode == XM_PAIR) ? timer.begin(st) : nullptr;
     FWI_HIP(launch_x_den<T>(d.M, mode, x_plan, dim3((d.nlines + lpb - 1) / lpb, B), st, a));

@@ -38,6 +38,9 @@ namespace fwi {
 // FWI_PITCH_BYTES      the spectrum row pitch px is a multiple of this
 // FWI_XVEL_LDS_BUDGET  x-lines per X1 workgroup = budget / (M sizeof(T)), odd
 // FWI_XDEN_LDS_BUDGET  the same for X2 (and the lossy density pass)
+// FWI_XDEN_PAIR_LDS_BUDGET  the same for the paired (adjoint + TR) X2: one line
+//                      at M = 224 FP32 (0.79 ms per launch against 0.83 with
+//                      three; the forward X2 is faster with three, 0.35 vs 0.42)
 // FWI_XEOS_LDS_BUDGET  the same for the lossy equation-of-state pass (3, 5, 7
 //                      lines at M = 224 FP32: 192, 221, 210 us per launch)
 // Measured on the 448x448x224 FP32 gradient (same box, alternating runs):
@@ -63,6 +66,9 @@ namespace fwi {
 #endif
 #ifndef FWI_XDEN_LDS_BUDGET
 #define FWI_XDEN_LDS_BUDGET 3072
+#endif
+#ifndef FWI_XDEN_PAIR_LDS_BUDGET
+#define FWI_XDEN_PAIR_LDS_BUDGET 896
 #endif
 #ifndef FWI_XEOS_LDS_BUDGET
 #define FWI_XEOS_LDS_BUDGET 3072
@@ -117,6 +123,10 @@ template <typename T> constexpr int odd_lpb(int budget, int M) {
 }
 template <typename T> constexpr int x_lpb_vel(int M) { return odd_lpb<T>(FWI_XVEL_LDS_BUDGET, M); }
 template <typename T> constexpr int x_lpb_den(int M) { return odd_lpb<T>(FWI_XDEN_LDS_BUDGET, M); }
+// lines per X2 workgroup of mode m (XMode: 1 = the paired adjoint + TR pass)
+template <typename T> constexpr int x_lpb_den_mode(int M, int m) {
+  return m == 1 ? odd_lpb<T>(FWI_XDEN_PAIR_LDS_BUDGET, M) : x_lpb_den<T>(M);
+}
 template <typename T> constexpr int x_lpb_eos(int M) { return odd_lpb<T>(FWI_XEOS_LDS_BUDGET, M); }
 template <typename T> constexpr int x_lpb(int M) { return odd_lpb<T>(4096, M); }
 constexpr int X_NT = 256;
@@ -1223,7 +1233,7 @@ __device__ __forceinline__ T p_at(const cplx<T>* bufp, int pcol, int l, int x) {
 template <typename T, int M, int MODE, int PL = 0>
 __global__ void __launch_bounds__(X_NT) k_x_density(X2Args<T> a) {
   using C = cplx<T>;
-  constexpr int LPB = x_lpb_den<T>(M);
+  constexpr int LPB = x_lpb_den_mode<T>(M, MODE);
   constexpr int NP = (MODE == XM_PAIR) ? 2 : 1;
   constexpr int TWP = 3 * LPB;        // d-_a v_a of the three axes
   constexpr int TWPP = NP * LPB;      // new pressure(s), packed for the R2C
