@@ -26,9 +26,23 @@ if ROOT not in sys.path:
 
 METRIC = "Mcell-steps/s of TR-gradient at 448x448x224 FP32; p50/p99 solve latency"
 PEAK_HBM_GBS = 8000.0
-# algorithmic HBM bytes per cell and simulation step of the eight-pass step
-# (40 field-sized reads and writes of 4 bytes; the pass table of the kernels)
-STEP_BYTES_PER_CELL = 160.0
+def step_bytes_per_cell(shape, pml) -> float:
+    """Algorithmic HBM bytes per cell and simulation step of the eight-pass
+    step (4-byte field-sized reads and writes; the pass table of the
+    kernels): 32 + 2 f + R passes, where f is the fraction of x-lines in a y
+    or z PML slab (they keep three split densities and two derivative
+    spectra; the others keep the undamped density sum, plus rho_x on the
+    x-PML voxels, and one spectrum of d-_y v_y + d-_z v_z) and R the split
+    density reads and writes per voxel."""
+    nz, ny, nx = shape
+    px, py, pz = pml
+
+    def slab(i, n, p):
+        return i < p or i > n - 1 - p
+    f = sum(1 for z in range(nz) for y in range(ny) if slab(y, ny, py) or slab(z, nz, pz)) / (ny * nz)
+    xp = sum(1 for n in range(nx // 2) if slab(2 * n, nx, px) or slab(2 * n + 1, nx, px))
+    rho = 6.0 * f + (2.0 + 4.0 * xp / nx) * (1.0 - f)
+    return 4.0 * (32.0 + 2.0 * f + rho)
 
 KERNEL_SYMBOLS = {
     "y_fwd": "k_axis_y<float, {ny}, false, {ty}, {py}>",
@@ -268,6 +282,7 @@ def main():
             "bytes_per_launch": d["bytes_per_launch"],
         }
 
+    step_b = step_bytes_per_cell(prob.shape, prob.pml)
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -293,11 +308,11 @@ def main():
         },
         "roofline": roof,
         "whole_gradient": {
-            "bytes_per_cell_step": STEP_BYTES_PER_CELL,
+            "bytes_per_cell_step": round(step_b, 2),
             "executed_steps": executed_steps(prob.nt),
-            "achieved_GBps": round(STEP_BYTES_PER_CELL * cells * executed_steps(prob.nt) * args.steps
+            "achieved_GBps": round(step_b * cells * executed_steps(prob.nt) * args.steps
                                    / total / 1e9, 1),
-            "frac": round(STEP_BYTES_PER_CELL * cells * executed_steps(prob.nt) * args.steps
+            "frac": round(step_b * cells * executed_steps(prob.nt) * args.steps
                           / total / 1e9 / PEAK_HBM_GBS, 4),
         },
         "per_pass": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}

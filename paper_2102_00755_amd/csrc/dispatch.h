@@ -33,6 +33,9 @@ template <typename T>
 hipError_t launch_axis_zp(int L, int tb, int plan, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
 template <typename T>
 hipError_t launch_axis_ys(int L, int tb, int plan, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
+// the inverse y pass of the time step (k_axis_y_div, grid.y = slots)
+template <typename T>
+hipError_t launch_axis_yd(int L, int tb, int plan, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
 template <typename T>
 hipError_t launch_axis_yv(int L, int tb, int plan, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
 // absorption z pass (k_axis_z_frac)

@@ -562,6 +562,7 @@ template <typename T> struct Engine : EngineBase {
     a.half_e0 = (T)((ypow - 1.0) / 2.0);
     a.half_e1 = (T)((ypow - 2.0) / 2.0);
     a.vz_state = 0;
+    for (int k = 0; k < 3; ++k) a.pml[k] = p.pml[k];
     return a;
   }
   // tiles per spectrum row of an axis pass of kind k (AxisKind)
@@ -573,24 +574,31 @@ template <typename T> struct Engine : EngineBase {
   // algorithmic bytes of one half spectrum / one real field
   double sbytes() const { return (double)(d.M + 1) * d.ny * d.nz * sizeof(C); }
   double fbytes() const { return (double)d.nfield * sizeof(T); }
-  // split-density reads + writes of one density step, in fields: 6 on the
-  // lines in a y or z PML slab, 2 plus rho_x on the x-PML pairs elsewhere
-  // (the storage of density_update)
-  double rho_fields() const {
+  // fraction of the x-lines in a y or z PML slab: they keep the three split
+  // densities and receive d-_y v_y and d-_z v_z apart; the others keep the
+  // undamped sum (+ rho_x on the x-PML pairs) and receive d-_y v_y + d-_z v_z
+  double full_line_frac() const {
     auto in = [](int i, int n, int P) { return i < P || i > n - 1 - P; };
-    long long full = 0, xp = 0;
+    long long full = 0;
     for (int z = 0; z < d.nz; ++z)
       for (int y = 0; y < d.ny; ++y) full += (in(y, d.ny, p.pml[1]) || in(z, d.nz, p.pml[2])) ? 1 : 0;
+    return (double)full / (double)d.nlines;
+  }
+  // split-density reads + writes of one density step, in fields: 6 on the
+  // full lines, 2 plus rho_x on the x-PML pairs elsewhere (density_update)
+  double rho_fields() const {
+    auto in = [](int i, int n, int P) { return i < P || i > n - 1 - P; };
+    long long xp = 0;
     for (int n = 0; n < d.M; ++n) xp += (in(2 * n, d.nx, p.pml[0]) || in(2 * n + 1, d.nx, p.pml[0])) ? 1 : 0;
-    const double acc = 6.0 * d.nx * full + (2.0 * d.nx + 4.0 * xp) * (double)(d.nlines - full);
-    return acc / ((double)d.nlines * d.nx);
+    const double f = full_line_frac();
+    return 6.0 * f + (2.0 + 4.0 * xp / d.nx) * (1.0 - f);
   }
 
   // Y3 .. Y2 of one step (six passes; X2 follows); half_only stops after the
   // velocity passes (Z2 with v_z, Y4 with v_y, X1 with v_x)
   int step_spectral(int slot0, int na, int slot1, int nslots, hipStream_t st, bool half_only = false) {
     const int ty = tile_bytes[AK_Y], tzm = tile_bytes[AK_ZMINUS], tzp = tile_bytes[AK_ZPLUS];
-    const dim3 gy(ntx(AK_Y) * d.nz, nslots * 1), gy3(ntx(AK_Y) * d.nz, nslots * 3);
+    const dim3 gy(ntx(AK_Y) * d.nz, nslots * 1);
     const dim3 gz(ntx(AK_ZPLUS) * d.ny, nslots), gz3(ntx(AK_ZMINUS) * d.ny, nslots * 3);
     const double S = sbytes(), F = fbytes(), ns = nslots;
     hipEvent_t ev;
@@ -622,8 +630,10 @@ template <typename T> struct Engine : EngineBase {
     FWI_HIP(launch_axis_zm<T>(d.nz, tzm, plans[AK_ZMINUS], gz3, st, a1));       // Z1
     timer.end(ev, FWI_PASS_Z_MINUS, 6 * ns * S, st);
     ev = timer.begin(st);
-    FWI_HIP(launch_axis_y<T>(d.ny, true, ty, plans[AK_Y], gy3, st, axis_args(slot0, na, slot1, 3, 0)));   // Y2
-    timer.end(ev, FWI_PASS_Y_INV, 6 * ns * S, st);
+    const int thalf = tile_bytes[AK_Y] / (int)sizeof(C) / 2;   // columns per field of a paired tile
+    const dim3 gy2((ntx(AK_Y) + (d.px + thalf - 1) / thalf) * d.nz, nslots);
+    FWI_HIP(launch_axis_yd<T>(d.ny, ty, plans[AK_Y], gy2, st, axis_args(slot0, na, slot1, 3, 0)));   // Y2
+    timer.end(ev, FWI_PASS_Y_INV, (5 + full_line_frac()) * ns * S, st);
     return FWI_OK;
   }
 
@@ -647,12 +657,14 @@ template <typename T> struct Engine : EngineBase {
     FWI_HIP(launch_x_den<T>(d.M, mode, x_plan, dim3((d.nlines + lpb - 1) / lpb, B), st, a));
     if (mode == XM_FWD) {
       // 3 spectra in, 1 out, split densities r/w, c0, source row, trace row, tape row
-      const double b = B * (4 * S + (1 + rho_fields()) * F + t * (d.n_src + d.n_rec + (a.tape ? d.n_bnd : 0)));
+      const double sp = 3 + full_line_frac();   // spectra read (the third on full lines only) and written
+      const double b = B * (sp * S + (1 + rho_fields()) * F + t * (d.n_src + d.n_rec + (a.tape ? d.n_bnd : 0)));
       timer.end(ev, FWI_PASS_X_DEN_FWD, b, st);
     } else if (mode == XM_PAIR) {
       // two simulations of (4 S + split densities), c0 once, adjoint source
       // row, tape row, ring (2 reads + 1 write), FP64 accumulator read + write
-      const double b = B * (2 * (4 * S + rho_fields() * F) + F + t * (d.n_rec + d.n_bnd + 3.0 * d.n_gam) + 16.0 * d.n_gam);
+      const double sp = 3 + full_line_frac();
+      const double b = B * (2 * (sp * S + rho_fields() * F) + F + t * (d.n_rec + d.n_bnd + 3.0 * d.n_gam) + 16.0 * d.n_gam);
       timer.end(ev, FWI_PASS_X_DEN_PAIR, b, st);
     }
     return FWI_OK;

@@ -169,6 +169,7 @@ template <typename T> struct AxisArgs {
   T half_e1;   //                  |k|^{2 half_e1} on field 1 (A[d]: (y - 2) / 2)
   int vz_state;  // time step: Z2 advances W_z (slot v[2]) with R instead of
                  // storing R, and Z1 reads field 2 from W_z
+  int pml[3];    // PML cells at both ends of x, y, z (Y2: storage of d-_y v_y, d-_z v_z)
 };
 
 __device__ __forceinline__ int slot_of(int i, int slot0, int na, int slot1) {
@@ -281,6 +282,91 @@ k_axis_y(AxisArgs<T> a) {
   __syncthreads();
   lds_fft<T, L, TW, TW, NT, INV, PL>(buf, twl);
   tile_store<T, L, TW, NT>(buf, g, px, ncol);
+}
+
+// Waves per SIMD the velocity y pass is compiled for: 4 (two workgroups of
+// 8 waves per CU) in FP32 where a thread holds at most 14 tile elements, else
+// the compiler's choice (FP64 would spill)
+template <typename T, int L, int TB> constexpr int yv_waves() {
+  return sizeof(T) == 4 &&
+                 (L * tile_tw<T, TB>() + axis_nt(L, tile_tw<T, TB>()) - 1) / axis_nt(L, tile_tw<T, TB>()) <= 14
+             ? 4
+             : 1;
+}
+
+// Inverse y pass of the time step (Y2), one launch per step (grid.y = slots).
+// The first ntx nz workgroups transform field 0 (d-_x v_x) in place in TW-wide
+// tiles.  The others transform fields 1 and 2 (d-_y v_y, d-_z v_z) side by
+// side: an LDS tile of TW columns holds the same TW/2 spectrum columns of both
+// fields.  On the x-lines outside the y and z PML slabs the density pass only
+// needs their sum (the split densities are stored compactly there, see
+// X2Args), so field 1 receives d-_y v_y + d-_z v_z, read from the two halves of
+// the tile, and field 2 is not written; lines in a slab receive both.  The
+// half-width tiles are XCD-paired like 64-byte z tiles.  L == ny.
+__device__ __forceinline__ bool in_pml_slab(int i, int n, int P) { return i < P || i > n - 1 - P; }
+template <typename T, int L, int TB, int PL = 0>
+__global__ void __launch_bounds__(axis_nt(L, tile_tw<T, TB>()))
+k_axis_y_div(AxisArgs<T> a) {
+  using C = cplx<T>;
+  constexpr int TW = tile_tw<T, TB>();
+  constexpr int H = TW / 2;                 // columns of each field in a paired tile
+  static_assert(TW % 2 == 0, "paired y tile: TW must be even");
+  constexpr int NT = axis_nt(L, TW);
+  constexpr int E = L * TW;
+  constexpr int EPT = (E + NT - 1) / NT;
+  constexpr int TPT = TwRegs<L, NT>::N_PER;
+  __shared__ C buf[L * TW];
+  __shared__ C twl[L];
+  const Slot<T>& sl = a.slots[slot_of(blockIdx.y, a.slot0, a.na, a.slot1)];
+  const size_t px = a.d.px;
+  const int ntx = ((int)px + TW - 1) / TW;
+  const int n0 = ntx * a.d.nz;              // field-0 workgroups
+  const int b = blockIdx.x;
+  if (b < n0) {
+    const int tile = b % ntx, z = b / ntx;
+    C* g = sl.spec[0] + (size_t)z * L * px + (size_t)tile * TW;
+    const int ncol = min(TW, (int)px - tile * TW);
+    tile_load<T, L, TW, NT>(buf, g, px, ncol, twl, a.tb.tw_y);
+    __syncthreads();
+    lds_fft<T, L, TW, TW, NT, true, PL>(buf, twl);
+    tile_store<T, L, TW, NT>(buf, g, px, ncol);
+    return;
+  }
+  const int nh = ((int)px + H - 1) / H;     // paired tiles per spectrum row
+  const int n1 = nh * a.d.nz;
+  int t1 = b - n0;
+  t1 = t1 < (n1 & ~15) ? (t1 & ~15) + 2 * (t1 & 7) + ((t1 >> 3) & 1) : t1;
+  const int tile = t1 % nh, z = t1 / nh;
+  const size_t off = (size_t)z * L * px + (size_t)tile * H;
+  const int ncol = min(H, (int)px - tile * H);
+  C* const g1 = sl.spec[1] + off;
+  C* const g2 = sl.spec[2] + off;
+  {
+    C tmp[EPT], tt[TPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = min((int)threadIdx.x + i * NT, E - 1);
+      const int c = e % TW;
+      tmp[i] = gld((c < H ? g1 : g2) + (size_t)(e / TW) * px + min(c % H, ncol - 1));
+    }
+    tw_prefetch<T, L, NT>(tt, a.tb.tw_y);
+    tile_commit<T, L, TW, NT>(buf, tmp);
+    tw_commit<T, L, NT>(twl, tt);
+  }
+  __syncthreads();
+  lds_fft<T, L, TW, TW, NT, true, PL>(buf, twl);
+  const bool zslab = in_pml_slab(z, a.d.nz, a.pml[2]);
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = (int)threadIdx.x + i * NT;
+    const int c = e % TW, cc = c % H;
+    if ((E % NT == 0 || e < E) && cc < ncol) {
+      const int y = e / TW;
+      const bool full = zslab || in_pml_slab(y, L, a.pml[1]);
+      if (c < H) gst(g1 + (size_t)y * px + cc, full ? buf[e] : cadd(buf[e], buf[e + H]));
+      else if (full) gst(g2 + (size_t)y * px + cc, buf[e]);
+    }
+  }
 }
 
 // Plain z pass: in-place FFT along z of nf fields per slot (grid transfers of
@@ -624,15 +710,6 @@ __device__ __forceinline__ void y_vel_update(cplx<T>* buf, const cplx<T>* twl, c
   tile_store<T, L, TW, NT>(buf, gout, px, ncol);
 }
 
-// Waves per SIMD the velocity y pass is compiled for: 4 (two workgroups of
-// 8 waves per CU) in FP32 where a thread holds at most 14 tile elements, else
-// the compiler's choice (FP64 would spill)
-template <typename T, int L, int TB> constexpr int yv_waves() {
-  return sizeof(T) == 4 &&
-                 (L * tile_tw<T, TB>() + axis_nt(L, tile_tw<T, TB>()) - 1) / axis_nt(L, tile_tw<T, TB>()) <= 14
-             ? 4
-             : 1;
-}
 template <typename T, int L, int TB, int PL = 0>
 __global__ void __launch_bounds__(axis_nt(L, tile_tw<T, TB>()))
 __attribute__((amdgpu_waves_per_eu(yv_waves<T, L, TB>()))) k_axis_y_vel(AxisArgs<T> a) {
@@ -997,14 +1074,14 @@ template <typename T> struct X2Args {
 // rho_z on the x-PML voxels), and in field 1 rho_x on the x-PML voxels only;
 // field 2 is not used there.  Lines in a y or z slab keep the three
 // components.  Same arithmetic, 2 + 4 P_x / nx instead of 6 field accesses
-// per voxel on those lines.
-__device__ __forceinline__ bool in_pml(int i, int n, int P) { return i < P || i > n - 1 - P; }
+// per voxel on those lines.  On the same lines the inverse y pass delivers
+// d-_y v_y + d-_z v_z as the second spectrum and no third one (k_axis_y_div).
 template <typename T> __device__ __forceinline__ bool full_split_line(const X2Args<T>& a, int line) {
-  return in_pml(line % a.d.ny, a.d.ny, a.pml[1]) || in_pml(line / a.d.ny, a.d.nz, a.pml[2]);
+  return in_pml_slab(line % a.d.ny, a.d.ny, a.pml[1]) || in_pml_slab(line / a.d.ny, a.d.nz, a.pml[2]);
 }
 // the voxel pair (2n, 2n+1) of an x-line touches the x PML
 template <typename T> __device__ __forceinline__ bool x_pml_pair(const X2Args<T>& a, int n) {
-  return in_pml(2 * n, a.d.nx, a.pml[0]) || in_pml(2 * n + 1, a.d.nx, a.pml[0]);
+  return in_pml_slab(2 * n, a.d.nx, a.pml[0]) || in_pml_slab(2 * n + 1, a.d.nx, a.pml[0]);
 }
 
 // Per-launch step indices of an X2 launch.
@@ -1088,7 +1165,16 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx
   });
   {
     C pre[SpecRegs<T, M, LPB, 3>::N], tt[XTw<M>::PER];
-    if (!no_step) x_prefetch_spectra<T, M, LPB, 3>(pre, sl.spec, l0, nl, px);
+    if (!no_step) {
+      // fields 0 and 1; field 2 only on the lines that keep the split (zeros
+      // elsewhere: field 1 holds d-_y v_y + d-_z v_z there)
+      x_prefetch_spectra<T, M, LPB, 2>(pre, sl.spec, l0, nl, px);
+      constexpr int PER = SpecRegs<T, M, LPB, 3>::PER;
+      lanes2d_all<LPB, M + 1>([&](int i, int l, int k, bool) {
+        const bool rd = l < nl && full_split_line(a, l0 + l);
+        pre[2 * PER + i] = rd ? gld(sl.spec[2] + (size_t)(l0 + l) * px + k) : cmake<C>((T)0, (T)0);
+      });
+    }
     if (STAGE_TW) x_tw_prefetch<T, M>(tt, a.tb);
     if (!no_step) x_commit_spectra<T, M, LPB, TWP, 3>(buf, pre, 0);
     if (STAGE_TW) x_tw_commit<T, M>(twl, tt);
