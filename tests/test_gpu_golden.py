@@ -67,6 +67,36 @@ def test_large_case_matches_stored_oracle(case):
     h.close()
 
 
+def test_full_workload_matches_oracle():
+    # the full-size measurement workload itself (448x448x224, PML 20, 32
+    # Rademacher-encoded emitters, 1024 receivers, the 4.95 M-voxel Gamma and
+    # its 1.24 M-voxel layer, 60 inclusions) on a 600-step horizon, in the
+    # launch configuration bench.py times (FP32, batch 1, library tuning)
+    import make_golden
+    from paper_2102_00755_amd.fwi import Handle
+    ref = np.load(os.path.join(GOLDEN, "fullcfg_oracle.npz"))
+    prob = make_golden.problem("fullcfg")
+    print(f"full workload shape={prob.shape} nt={prob.nt} gamma={int(prob.gamma.sum())}", flush=True)
+    w = oracle.rademacher(prob.enc_seed, prob.n_src)
+    assert np.array_equal(w, ref["w"])
+    h = Handle.from_problem(prob, precision=4)
+    S = torch.from_numpy(prob.src_signals())
+    wt = torch.from_numpy(w)
+    c = torch.from_numpy(prob.c_eval)
+    traces = h.forward(c, S, wt)[0].cpu().numpy()
+    mis, grad = h.gradient(c, S, wt, torch.from_numpy(ref["obs"]))
+    D = float(ref["misfit"])
+    g = prob.gamma.astype(bool)
+    got = grad[0].cpu().numpy()
+    errs = (rel(traces, ref["traces_eval"]), abs(float(mis[0]) - D) / D, rel(got[g], ref["grad_gamma"]))
+    print("full workload rel errors: traces %.2e misfit %.2e gradient %.2e" % errs, flush=True)
+    assert errs[0] < 1e-4
+    assert errs[1] <= 1e-3
+    assert errs[2] < 1e-3
+    assert np.all(got[~g] == 0)
+    h.close()
+
+
 def test_full_size_derivative_matches_oracle():
     # the spectral derivative of eq. DisPartDevSt on the 448x448x224 grid
     from oracle import kspace as ks
