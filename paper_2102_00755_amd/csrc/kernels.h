@@ -439,6 +439,25 @@ __device__ __forceinline__ void z_apply(cplx<T>* buf, const cplx<T>* m, const cp
   }
 }
 
+// Storage of W_z (the x-y spectrum of v_z, slot v[2]), which only the z
+// passes touch: z-contiguous bricks of WB = 64 bytes of columns,
+// [y][px / WB][nz][WB], so that a z tile reads and writes it as contiguous
+// 64-byte rows of one block (the spectra are [z][y][px], where a z tile's rows
+// lie ny px apart).  px is a multiple of WB and a z tile spans whole bricks.
+template <typename T> constexpr int wz_bw() { return 64 / (int)sizeof(cplx<T>); }
+// the first element of the tile of columns [k0, k0 + TW) at spectrum row y
+template <typename T>
+__device__ __forceinline__ size_t wz_tile(const Dims& d, int y, int k0) {
+  constexpr int WB = wz_bw<T>();
+  return ((size_t)y * (d.px / WB) + k0 / WB) * (size_t)d.nz * WB;
+}
+// offset of element (row r = z, column c) within the tile
+template <typename T, int L>
+__device__ __forceinline__ int wz_el(int r, int c) {
+  constexpr int WB = wz_bw<T>();
+  return (c / WB) * L * WB + r * WB + c % WB;
+}
+
 // Z pass of the velocity divergence terms: field f -> F_z^-1 m-_f F_z field f
 // (eq. DisPartDevSt with the minus shift).  L == nz.
 template <typename T, int L, int TB, int PL = 0>
@@ -460,14 +479,27 @@ k_axis_z_minus(AxisArgs<T> a) {
   const size_t rstride = (size_t)a.d.ny * px;
   const size_t off = (size_t)y * px + (size_t)tile * TW;
   C* g = a.slots[s].spec[f] + off;
-  const C* gin = (a.vz_state && f == 2) ? reinterpret_cast<const C*>(a.slots[s].v[2]) + off : g;
+  const bool wz_in = a.vz_state && f == 2;   // v_z from its z-contiguous state
   const int ncol = min(TW, (int)px - tile * TW);
   const int kx = min(tile * TW + (int)threadIdx.x % TW, a.d.M);
   T kap[EPT];
   C m[EPT];
   z_kappa<T, L, TW, NT>(a, kx, y, kap);
   z_mult<T, L, TW, NT>(a, a.tb.sfac_m, f, kx, y, kap, m);
-  tile_load<T, L, TW, NT>(buf, gin, rstride, ncol, twl, a.tb.tw_z);
+  if (wz_in) {
+    const C* gw = reinterpret_cast<const C*>(a.slots[s].v[2]) + wz_tile<T>(a.d, y, tile * TW);
+    C tmp[EPT], tt[TwRegs<L, NT>::N_PER];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = min((int)threadIdx.x + i * NT, L * TW - 1);
+      tmp[i] = gld(gw + wz_el<T, L>(e / TW, min(e % TW, ncol - 1)));
+    }
+    tw_prefetch<T, L, NT>(tt, a.tb.tw_z);
+    tile_commit<T, L, TW, NT>(buf, tmp);
+    tw_commit<T, L, NT>(twl, tt);
+  } else {
+    tile_load<T, L, TW, NT>(buf, g, rstride, ncol, twl, a.tb.tw_z);
+  }
   __syncthreads();
   lds_fft<T, L, TW, TW, NT, false, PL>(buf, twl);
   z_apply<T, L, TW, NT>(buf, m, nullptr);
@@ -541,10 +573,14 @@ k_axis_z_plus(AxisArgs<T> a) {
     tile_store<T, L, TW, NT>(buf, s2 + off, rstride, ncol);
     return;
   }
-  C* const gw = reinterpret_cast<C*>(a.slots[s].v[2]) + off;
+  C* const gw = reinterpret_cast<C*>(a.slots[s].v[2]) + wz_tile<T>(a.d, y, tile * TW);
   C w[EPT];
   T lz[EPT];
-  tile_prefetch<T, L, TW, NT>(w, gw, rstride, ncol);
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = min((int)threadIdx.x + i * NT, L * TW - 1);
+    w[i] = gld(gw + wz_el<T, L>(e / TW, min(e % TW, ncol - 1)));
+  }
 #pragma unroll
   for (int i = 0; i < EPT; ++i) lz[i] = gld(a.tb.pml_s[2] + min(((int)threadIdx.x + i * NT) / TW, L - 1));
   const T cf = a.vcoef * (T)a.d.ny;
@@ -554,7 +590,7 @@ k_axis_z_plus(AxisArgs<T> a) {
     if (((L * TW) % NT == 0 || e < L * TW) && e % TW < ncol) {
       const C r = buf[e];
       const C wn = cmake<C>(lz[i] * (lz[i] * w[i].x - cf * r.x), lz[i] * (lz[i] * w[i].y - cf * r.y));
-      gst(gw + (size_t)(e / TW) * rstride + e % TW, wn);
+      gst(gw + wz_el<T, L>(e / TW, e % TW), wn);
     }
   }
 }
