@@ -249,12 +249,13 @@ int fwi_set_tuning(fwi_handle* h, const fwi_tuning* t);
  *                 except for alpha0 == 0 && alpha0_field == NULL, which
  *                 switches absorption off); read by every later call, so it
  *                 must stay allocated while absorption is set (the caller owns it)
- * The lossy step replaces the fused X2 pass by five launches (density
- * update, forward y, absorption z pass, inverse y, equation of state);
- * FWI_GRAPH replays it as a step graph like the lossless step;
- * FWI_TR_FINAL_STATE is rejected with FWI_ERR_INVALID_ARG.  The first call that switches absorption
- * on allocates batch x |Gamma| values of device memory (FWI_ERR_OOM on
- * failure).  Any call invalidates the saved tape.  Errors:
+ * The lossy step forms A[d] in its velocity-divergence z pass and replaces
+ * the fused X2 pass by five launches (density update, forward y, absorption
+ * z pass of B[s], inverse y, equation of state); FWI_GRAPH replays it as a
+ * step graph like the lossless step; FWI_TR_FINAL_STATE is rejected with
+ * FWI_ERR_INVALID_ARG.  The first call that switches absorption on allocates
+ * batch x |Gamma| values and two half spectra per problem of device memory
+ * (FWI_ERR_OOM on failure).  Any call invalidates the saved tape.  Errors:
  * FWI_ERR_INVALID_ARG (nothing changed) for a NULL handle, alpha0 < 0 or not
  * finite, or y outside the range. */
 int fwi_set_absorption(fwi_handle* h, double alpha0, double y, const void* alpha0_field, int32_t tr_flip);

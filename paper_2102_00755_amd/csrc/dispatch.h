@@ -29,6 +29,9 @@ template <typename T>
 hipError_t launch_axis_z(int L, bool inv, int tb, int plan, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
 template <typename T>
 hipError_t launch_axis_zm(int L, int tb, int plan, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
+// the Z1 of the lossy step with the A[d] output (k_axis_z_minus_ad, grid.y = slots)
+template <typename T>
+hipError_t launch_axis_zma(int L, int tb, int plan, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
 template <typename T>
 hipError_t launch_axis_zp(int L, int tb, int plan, dim3 grid, hipStream_t st, const AxisArgs<T>& a);
 template <typename T>

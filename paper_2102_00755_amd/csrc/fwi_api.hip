@@ -367,6 +367,9 @@ template <typename T> struct Engine : EngineBase {
   bool tr_flip = true;
   DevBuf mem_padj;
   T* padj = nullptr;
+  // A[d] spectrum per slot (the lossy Z1 writes it, Y2 and the lossy EOS read it)
+  DevBuf mem_ad;
+  C* ad_ptr = nullptr;
   // exact gradient (FWI_EXACT): dp/dc0 history on Gamma [nt][n_gam] and the
   // linear voxel index of every receiver (allocated on first use)
   DevBuf mem_hist, mem_rec_lin;
@@ -563,6 +566,9 @@ template <typename T> struct Engine : EngineBase {
     a.half_e1 = (T)((ypow - 2.0) / 2.0);
     a.vz_state = 0;
     for (int k = 0; k < 3; ++k) a.pml[k] = p.pml[k];
+    a.ad = nullptr;
+    a.ad_stride = d.nspec;
+    a.ad_coef = (T)p.rho0;
     return a;
   }
   // tiles per spectrum row of an axis pass of kind k (AxisKind)
@@ -627,13 +633,20 @@ template <typename T> struct Engine : EngineBase {
     ev = timer.begin(st);
     AxisArgs<T> a1 = axis_args(slot0, na, slot1, 3, 0);
     a1.vz_state = 1;
-    FWI_HIP(launch_axis_zm<T>(d.nz, tzm, plans[AK_ZMINUS], gz3, st, a1));       // Z1
-    timer.end(ev, FWI_PASS_Z_MINUS, 6 * ns * S, st);
+    if (lossy) {   // with A[d] of the absorption operator: one workgroup per tile and slot
+      a1.ad = ad_ptr;
+      FWI_HIP(launch_axis_zma<T>(d.nz, tzm, plans[AK_ZMINUS], dim3(ntx(AK_ZMINUS) * d.ny, nslots), st, a1));  // Z1 + A[d]
+    } else {
+      FWI_HIP(launch_axis_zm<T>(d.nz, tzm, plans[AK_ZMINUS], gz3, st, a1));  // Z1
+    }
+    timer.end(ev, FWI_PASS_Z_MINUS, (lossy ? 7 : 6) * ns * S, st);
     ev = timer.begin(st);
     const int thalf = tile_bytes[AK_Y] / (int)sizeof(C) / 2;   // columns per field of a paired tile
-    const dim3 gy2((ntx(AK_Y) + (d.px + thalf - 1) / thalf) * d.nz, nslots);
-    FWI_HIP(launch_axis_yd<T>(d.ny, ty, plans[AK_Y], gy2, st, axis_args(slot0, na, slot1, 3, 0)));   // Y2
-    timer.end(ev, FWI_PASS_Y_INV, (5 + full_line_frac()) * ns * S, st);
+    const dim3 gy2(((lossy ? 2 : 1) * ntx(AK_Y) + (d.px + thalf - 1) / thalf) * d.nz, nslots);
+    AxisArgs<T> a2 = axis_args(slot0, na, slot1, 3, 0);
+    if (lossy) a2.ad = ad_ptr;
+    FWI_HIP(launch_axis_yd<T>(d.ny, ty, plans[AK_Y], gy2, st, a2));   // Y2 (+ A[d])
+    timer.end(ev, FWI_PASS_Y_INV, (5 + full_line_frac() + (lossy ? 2 : 0)) * ns * S, st);
     return FWI_OK;
   }
 
@@ -648,6 +661,8 @@ template <typename T> struct Engine : EngineBase {
     a.delay = delays_on ? delay : nullptr;
     a.hist = hist_ptr;
     for (int k = 0; k < 3; ++k) a.pml[k] = p.pml[k];
+    a.ad = ad_ptr;
+    a.ad_stride = d.nspec;
     return a;
   }
   int launch_x2(int mode, int B, const X2Args<T>& a, hipStream_t st) {
@@ -692,10 +707,11 @@ template <typename T> struct Engine : EngineBase {
     const int s1 = (k1 < 0) ? s0 : ((k1 == SP_ADJOINT) ? 0 : p.batch);
     const int ns = (k1 < 0) ? B : 2 * B;
     const int ty = tile_bytes[AK_Y], tz = tile_bytes[AK_ZMINUS];
-    const AxisArgs<T> ax = axis_args(s0, B, s1, 2, 0);
-    FWI_HIP(launch_axis_y<T>(d.ny, false, ty, plans[AK_Y], dim3(ntx(AK_Y) * d.nz, ns * 2), st, ax));
-    FWI_HIP(launch_axis_zf<T>(d.nz, tz, plans[AK_ZMINUS], dim3(ntx(AK_ZMINUS) * d.ny, ns * 2), st, ax));
-    FWI_HIP(launch_axis_y<T>(d.ny, true, ty, plans[AK_Y], dim3(ntx(AK_Y) * d.nz, ns * 2), st, ax));
+    // B[s] only: A[d] came with the step's Z1
+    const AxisArgs<T> ax = axis_args(s0, B, s1, 1, 0);
+    FWI_HIP(launch_axis_y<T>(d.ny, false, ty, plans[AK_Y], dim3(ntx(AK_Y) * d.nz, ns), st, ax));
+    FWI_HIP(launch_axis_zf<T>(d.nz, tz, plans[AK_ZMINUS], dim3(ntx(AK_ZMINUS) * d.ny, ns), st, ax));
+    FWI_HIP(launch_axis_y<T>(d.ny, true, ty, plans[AK_Y], dim3(ntx(AK_Y) * d.nz, ns), st, ax));
     const int lpe = x_lines_per_block_eos<T>(d.M);
     const dim3 ge((d.nlines + lpe - 1) / lpe, B);
     FWI_HIP(launch_x_lossy<T>(d.M, 1, k0, ge, st, a));
@@ -785,6 +801,15 @@ template <typename T> struct Engine : EngineBase {
         return fail(FWI_ERR_OOM, "device allocation of " + std::to_string(n) + " bytes failed");
       }
       padj = (T*)mem_padj.p;
+    }
+    if (!mem_ad.p) {
+      FWI_HIP(hipSetDevice(device));
+      const size_t n = (size_t)2 * p.batch * (size_t)d.nspec * sizeof(C);
+      if (hipMalloc(&mem_ad.p, n) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(FWI_ERR_OOM, "device allocation of " + std::to_string(n) + " bytes failed");
+      }
+      ad_ptr = (C*)mem_ad.p;
     }
     tape_valid = false;
     lossy = true;

@@ -170,6 +170,12 @@ template <typename T> struct AxisArgs {
   int vz_state;  // time step: Z2 advances W_z (slot v[2]) with R instead of
                  // storing R, and Z1 reads field 2 from W_z
   int pml[3];    // PML cells at both ends of x, y, z (Y2: storage of d-_y v_y, d-_z v_z)
+  // absorption: the spectrum A[d] per slot (slot s at ad + s ad_stride),
+  // written by the Z1 of the lossy step, inverse-y transformed by Y2; null
+  // without absorption.  ad_coef = rho0.
+  cplx<T>* ad;
+  long long ad_stride;
+  T ad_coef;
 };
 
 __device__ __forceinline__ int slot_of(int i, int slot0, int na, int slot1) {
@@ -296,7 +302,7 @@ template <typename T, int L, int TB> constexpr int yv_waves() {
 
 // Inverse y pass of the time step (Y2), one launch per step (grid.y = slots).
 // The first ntx nz workgroups transform field 0 (d-_x v_x) in place in TW-wide
-// tiles.  The others transform fields 1 and 2 (d-_y v_y, d-_z v_z) side by
+// tiles (with absorption the next ntx nz the slot's A[d] spectrum).  The others transform fields 1 and 2 (d-_y v_y, d-_z v_z) side by
 // side: an LDS tile of TW columns holds the same TW/2 spectrum columns of both
 // fields.  On the x-lines outside the y and z PML slabs the density pass only
 // needs their sum (the split densities are stored compactly there, see
@@ -322,9 +328,12 @@ k_axis_y_div(AxisArgs<T> a) {
   const int ntx = ((int)px + TW - 1) / TW;
   const int n0 = ntx * a.d.nz;              // field-0 workgroups
   const int b = blockIdx.x;
-  if (b < n0) {
-    const int tile = b % ntx, z = b / ntx;
-    C* g = sl.spec[0] + (size_t)z * L * px + (size_t)tile * TW;
+  const int nad = a.ad ? n0 : 0;            // A[d] workgroups (absorption)
+  if (b < n0 + nad) {
+    const int bb = b < n0 ? b : b - n0;
+    const int tile = bb % ntx, z = bb / ntx;
+    C* const base = b < n0 ? sl.spec[0] : a.ad + (size_t)slot_of(blockIdx.y, a.slot0, a.na, a.slot1) * a.ad_stride;
+    C* g = base + (size_t)z * L * px + (size_t)tile * TW;
     const int ncol = min(TW, (int)px - tile * TW);
     tile_load<T, L, TW, NT>(buf, g, px, ncol, twl, a.tb.tw_y);
     __syncthreads();
@@ -334,7 +343,7 @@ k_axis_y_div(AxisArgs<T> a) {
   }
   const int nh = ((int)px + H - 1) / H;     // paired tiles per spectrum row
   const int n1 = nh * a.d.nz;
-  int t1 = b - n0;
+  int t1 = b - n0 - nad;
   t1 = t1 < (n1 & ~15) ? (t1 & ~15) + 2 * (t1 & 7) + ((t1 >> 3) & 1) : t1;
   const int tile = t1 % nh, z = t1 / nh;
   const size_t off = (size_t)z * L * px + (size_t)tile * H;
@@ -508,6 +517,101 @@ k_axis_z_minus(AxisArgs<T> a) {
   tile_store<T, L, TW, NT>(buf, g, rstride, ncol);
 }
 
+// x^e for normal x > 0 in the kernel's precision.  FP32: 2^(e log2 x) with
+// the hardware base-2 logarithm and exponential (about 1 ulp each, a relative
+// error near 1e-6 here, against ~100 instructions of powf, which made the
+// absorption passes ALU-bound); FP64: pow.
+__device__ __forceinline__ float real_pow(float x, float e) {
+  return __builtin_amdgcn_exp2f(e * __builtin_amdgcn_logf(x));
+}
+__device__ __forceinline__ double real_pow(double x, double e) { return pow(x, e); }
+
+// Z1 of the lossy step: one workgroup per tile runs the three fields of
+// k_axis_z_minus one after the other and also forms the absorption term
+// A[d] = F^-1 |k|^{y-2} F d of d = rho0 sum_a d-_a v_a (Sec. 2.1) from the same
+// z spectra: the products m_a F v_a of the three fields are summed in
+// registers, multiplied by rho0 |k|^{y-2} (0 at k = 0; the 1/(nx ny nz) of
+// the unnormalised transforms is already in m_a) and inverse z transformed
+// into the slot's A[d] spectrum, which the inverse y pass then finishes.
+// L == nz.
+template <typename T, int L, int TB, int PL = 0>
+__global__ void __launch_bounds__(axis_nt(L, tile_tw<T, TB>()))
+k_axis_z_minus_ad(AxisArgs<T> a) {
+  using C = cplx<T>;
+  constexpr int TW = tile_tw<T, TB>();
+  constexpr int NT = axis_nt(L, TW);
+  constexpr int EPT = (L * TW + NT - 1) / NT;
+  __shared__ C buf[L * TW];
+  __shared__ C twl[L];
+  const int ntx = (a.d.px + TW - 1) / TW;   // tiles per spectrum row
+  const int tl = tile_linear<TB>();
+  const int tile = tl % ntx;
+  const int y = tl / ntx;
+  const int s = slot_of(blockIdx.y, a.slot0, a.na, a.slot1);
+  const size_t px = a.d.px;
+  const size_t rstride = (size_t)a.d.ny * px;
+  const size_t off = (size_t)y * px + (size_t)tile * TW;
+  const int ncol = min(TW, (int)px - tile * TW);
+  const int kx = min(tile * TW + (int)threadIdx.x % TW, a.d.M);
+  T kap[EPT];
+  C acc[EPT];
+  z_kappa<T, L, TW, NT>(a, kx, y, kap);
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) acc[i] = cmake<C>((T)0, (T)0);
+  for (int f = 0; f < 3; ++f) {
+    C* g = a.slots[s].spec[f] + off;
+    C m[EPT];
+    z_mult<T, L, TW, NT>(a, a.tb.sfac_m, f, kx, y, kap, m);
+    if (f == 0) {
+      tile_load<T, L, TW, NT>(buf, g, rstride, ncol, twl, a.tb.tw_z);
+    } else {
+      C tmp[EPT];
+      if (f == 2 && a.vz_state) {
+        const C* gw = reinterpret_cast<const C*>(a.slots[s].v[2]) + wz_tile<T>(a.d, y, tile * TW);
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+          const int e = min((int)threadIdx.x + i * NT, L * TW - 1);
+          tmp[i] = gld(gw + wz_el<T, L>(e / TW, min(e % TW, ncol - 1)));
+        }
+      } else {
+        tile_prefetch<T, L, TW, NT>(tmp, g, rstride, ncol);
+      }
+      __syncthreads();   // the previous field's stores have read buf
+      tile_commit<T, L, TW, NT>(buf, tmp);
+    }
+    __syncthreads();
+    lds_fft<T, L, TW, TW, NT, false, PL>(buf, twl);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = (int)threadIdx.x + i * NT;
+      if ((L * TW) % NT == 0 || e < L * TW) {
+        const C v = cmul(m[i], buf[e]);
+        buf[e] = v;
+        acc[i] = cadd(acc[i], v);
+      }
+    }
+    __syncthreads();
+    lds_fft<T, L, TW, TW, NT, true, PL>(buf, twl);
+    tile_store<T, L, TW, NT>(buf, g, rstride, ncol);
+  }
+  // A[d]: rho0 |k|^{y-2} times the summed spectra
+  const T base = a.tb.ksq[0][kx] + a.tb.ksq[1][y];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = (int)threadIdx.x + i * NT;
+    const int r = (int)threadIdx.x / TW + i * (NT / TW);
+    if ((L * TW) % NT == 0 || e < L * TW) {
+      const T q = base + a.tb.ksq[2][r];
+      const T mA = q > (T)0 ? real_pow(q, a.half_e1) * a.ad_coef : (T)0;
+      buf[e] = cscale(acc[i], mA);
+    }
+  }
+  __syncthreads();
+  lds_fft<T, L, TW, TW, NT, true, PL>(buf, twl);
+  tile_store<T, L, TW, NT>(buf, a.ad + (size_t)s * a.ad_stride + off, rstride, ncol);
+}
+
 // Z pass of the pressure gradient, field 0 (p_hat) -> two fields:
 //   field 0: Q = F_z^-1 kappa F_z p_hat                (for d+_x and d+_y)
 //   field 2: R = F_z^-1 kappa i k_z e^{+i k_z dz/2} F_z p_hat   (d+_z)
@@ -594,15 +698,6 @@ k_axis_z_plus(AxisArgs<T> a) {
     }
   }
 }
-
-// x^e for normal x > 0 in the kernel's precision.  FP32: 2^(e log2 x) with
-// the hardware base-2 logarithm and exponential (about 1 ulp each, a relative
-// error near 1e-6 here, against ~100 instructions of powf, which made the
-// absorption passes ALU-bound); FP64: pow.
-__device__ __forceinline__ float real_pow(float x, float e) {
-  return __builtin_amdgcn_exp2f(e * __builtin_amdgcn_logf(x));
-}
-__device__ __forceinline__ double real_pow(double x, double e) { return pow(x, e); }
 
 // Z pass of the absorption operators (Sec. 2.1, the fractional Laplacians of
 // L): field f -> F_z^-1 m_f F_z field f with the radial multiplier
@@ -1099,6 +1194,8 @@ template <typename T> struct X2Args {
   // step (problem 0), or null
   T* hist;
   int pml[3];            // PML cells at both ends of x, y, z (normal grid: Lambda != 1 there)
+  const cplx<T>* ad;     // absorption: A[d] per slot (AxisArgs::ad), read by the lossy EOS
+  long long ad_stride;
 };
 
 // Storage of the split densities (three real fields per slot).  Inside the
@@ -1163,10 +1260,9 @@ __device__ __forceinline__ int local_line(const int32_t* off, int l0, int nl, in
 // only), 2 = keep the stored densities (TR start from the final forward state)
 // STAGE_TW: this call also stages the x twiddles in twl (the first call of
 // the workgroup); later calls find them there.
-// LOSSY: instead of p, column pcol receives s = sum_a rho_a and column
-// pcol + LPB receives d = rho0 sum_a d-_a v_a (0 without a density step), and
-// s is also stored as a real field in the slot's third spectrum buffer (rows
-// of px complex), for the lossy equation of state.
+// LOSSY: instead of p, column pcol receives s = sum_a rho_a, which is also
+// stored as a real field in the slot's third spectrum buffer (rows of px
+// complex), for the lossy equation of state (A[d] comes from the z pass).
 template <typename T, int M, int LPB, int TWP, int TWPP, int KIND, bool STAGE_TW, bool LOSSY = false, int PL = 0>
 __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx& si, const Slot<T>& sl, int b,
                                                int l0, int nl, int state_mode, int pcol, cplx<T>* buf,
@@ -1270,7 +1366,6 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx
     const C c2 = cc[i];
     const C sv = spv[n * LPB + l];
     C sum = cmake<C>((T)0, (T)0);
-    C dsum = cmake<C>((T)0, (T)0);
     if (!full_split_line(a, line)) {
       // undamped part u in field 0, rho_x on the x-PML pairs in field 1
       const bool xp = x_pml_pair(a, n);
@@ -1283,7 +1378,6 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx
         rx = rr[i][1];
       } else {
         const C d0 = buf[n * TWP + l], d1 = buf[n * TWP + LPB + l], d2 = buf[n * TWP + 2 * LPB + l];
-        if (LOSSY) dsum = cadd(cadd(d0, d1), d2);
         const C du = xp ? cadd(d1, d2) : cadd(cadd(d0, d1), d2);
         u = cmake<C>(rr[i][0].x - a.dt_rho0 * du.x, rr[i][0].y - a.dt_rho0 * du.y);
         if (xp) {
@@ -1313,7 +1407,6 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx
         rn = rr[i][f];
       } else {
         const C dv = buf[n * TWP + f * LPB + l];
-        if (LOSSY) dsum = cadd(dsum, dv);
         const T lx = f == 0 ? l0f[i].x : (f == 1 ? l1f[i] : l2f[i]);
         const T ly = f == 0 ? l0f[i].y : (f == 1 ? l1f[i] : l2f[i]);
         rn = cmake<C>(lx * (lx * rr[i][f].x - a.dt_rho0 * dv.x), ly * (ly * rr[i][f].y - a.dt_rho0 * dv.y));
@@ -1329,7 +1422,6 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx
     }
     if (LOSSY) {
       bufp[n * TWPP + pcol + l] = sum;
-      bufp[n * TWPP + pcol + LPB + l] = cmake<C>(a.rho0 * dsum.x, a.rho0 * dsum.y);
       gst(sl.spec[2] + (size_t)line * px + n, sum);
     } else {
       bufp[n * TWPP + pcol + l] = cmake<C>(c2.x * c2.x * sum.x, c2.y * c2.y * sum.y);
@@ -1457,14 +1549,14 @@ __global__ void __launch_bounds__(X_NT) k_x_density(X2Args<T> a) {
 // XL1: C2R of d-_a v_a, split-density update with PML and the injection or
 // imposition of KIND (SP_SOURCE forward, SP_ADJOINT adjoint, SP_DIRICHLET TR
 // with a.tr_state_mode as in X2), then s = sum_a rho_a (also kept as a real
-// field in the third spectrum buffer) and d = rho0 sum_a d-_a v_a, whose
-// forward x transforms go to fields 0 (s) and 1 (d).
+// field in the third spectrum buffer), whose forward x transform goes to
+// field 0.  (A[d] of d = rho0 sum_a d-_a v_a is formed by the lossy Z1.)
 template <typename T, int M, int KIND>
 __global__ void __launch_bounds__(X_NT) k_x_lossy_rho(X2Args<T> a) {
   using C = cplx<T>;
   constexpr int LPB = x_lpb_den<T>(M);
   constexpr int TWP = 3 * LPB;        // d-_a v_a of the three axes
-  constexpr int TWPP = 2 * LPB;       // s and d
+  constexpr int TWPP = LPB;           // s
   __shared__ C buf[(M + 1) * TWP];
   __shared__ C bufp[(M + 1) * TWPP];
   __shared__ C spv[M * LPB];
@@ -1483,12 +1575,13 @@ __global__ void __launch_bounds__(X_NT) k_x_lossy_rho(X2Args<T> a) {
   lds_fft<T, M, TWPP, TWPP, X_NT, false>(bufp, twl);
   r2c_post<T, M, TWPP, TWPP>(bufp, twl + M);
   __syncthreads();
-  cplx<T>* specs[2] = {sl.spec[0], sl.spec[1]};
-  x_store_spectra<T, M, LPB, TWPP, 2>(bufp, specs, 0, l0, nl, a.d.px);
+  cplx<T>* specs[1] = {sl.spec[0]};
+  x_store_spectra<T, M, LPB, TWPP, 1>(bufp, specs, 0, l0, nl, a.d.px);
 }
 
-// XL2: C2R of fields 0 (B[s] = F^-1 |k|^{y-1} F s) and 1 (A[d] =
-// F^-1 |k|^{y-2} F d), lossy equation of state
+// XL2: C2R of field 0 (B[s] = F^-1 |k|^{y-1} F s) and of the slot's A[d] =
+// F^-1 |k|^{y-2} F d (zero when the TR starts without a density step), lossy
+// equation of state
 //   p = c0^2 (s + sgn tau A[d] - eta B[s]),
 //   tau = -2 alpha0 c0^{y-1},  eta = 2 alpha0 c0^y tan(pi y / 2),
 // sgn = a.tr_tau_sign for the TR (KIND SP_DIRICHLET), else +1; then the
@@ -1522,9 +1615,16 @@ __global__ void __launch_bounds__(X_NT) k_x_lossy_eos(X2Args<T> a) {
                      : cmake<C>(a.alpha0_u, a.alpha0_u);
   });
   {
+    const bool no_step = KIND == SP_DIRICHLET && a.tr_state_mode != 0;
+    cplx<T>* specs[2] = {sl.spec[0],
+                         const_cast<C*>(a.ad) + (size_t)(KIND == SP_ADJOINT ? b : a.tr_off + b) * a.ad_stride};
     C pre[SpecRegs<T, M, LPB, 2>::N], tt[XTw<M>::PER];
-    x_prefetch_spectra<T, M, LPB, 2>(pre, sl.spec, l0, nl, px);
+    x_prefetch_spectra<T, M, LPB, 2>(pre, specs, l0, nl, px);
     x_tw_prefetch<T, M>(tt, a.tb);
+    if (no_step) {
+#pragma unroll
+      for (int i = 0; i < SpecRegs<T, M, LPB, 2>::PER; ++i) pre[SpecRegs<T, M, LPB, 2>::PER + i] = cmake<C>((T)0, (T)0);
+    }
     x_commit_spectra<T, M, LPB, TWP, 2>(buf, pre, 0);
     x_tw_commit<T, M>(twl, tt);
   }
