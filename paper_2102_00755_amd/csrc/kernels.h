@@ -13,10 +13,13 @@
 //   Y1  forward y-FFT of the x spectrum of v_x        (1 field)
 //   Z1  forward z-FFT, x kappa * i k_a e^{-i k_a dx/2}, inverse z-FFT
 //       (v_z: read from W_z, which it leaves in place)
-//   Y2  inverse y-FFT                                 (3 fields)
-//   X2  inverse x (C2R) -> d-_a v_a, split-density update with PML, source /
-//       adjoint injection or Dirichlet imposition, equation of state, sensor
+//   Y2  inverse y-FFT of the 3 fields; d-_y v_y + d-_z v_z summed on the
+//       x-lines outside the y and z PML slabs
+//   X2  inverse x (C2R) -> d-_a v_a, split-density update with PML (the
+//       densities kept compactly outside the slabs), source / adjoint
+//       injection or Dirichlet imposition, equation of state, sensor
 //       sampling, boundary tape, gradient accumulation, forward x (R2C) of p
+// With absorption Z1 also forms A[d] and X2 is replaced by the lossy passes.
 // The k-space operator kappa = sinc(c_ref dt |k| / 2) is evaluated on the
 // fly (a Taylor series in u = (c_ref dt |k| / 2)^2) instead of being read
 // from HBM, and the 1/(nx ny nz) normalisation of the three unnormalised
