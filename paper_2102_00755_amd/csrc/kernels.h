@@ -46,17 +46,18 @@ namespace fwi {
 //                      three; the forward X2 is faster with three, 0.35 vs 0.42)
 // FWI_XEOS_LDS_BUDGET  the same for the lossy equation-of-state pass (3, 5, 7
 //                      lines at M = 224 FP32: 192, 221, 210 us per launch)
-// Measured on the 448x448x224 FP32 gradient (same box, alternating runs):
-// 128-byte y tiles with 64-byte z tiles (XCD-paired, see tile_linear) give
-// 25 140 Mcell-steps/s against 24 995 with 128-byte z tiles and 24 600 with
-// 64-byte y tiles; the pitch stays 128 bytes (a 64-byte pitch makes half of
+// Measured on the 448x448x224 FP32 gradient (same box, alternating runs),
+// with the nine-pass step: 128-byte y tiles with 64-byte z tiles (XCD-paired,
+// see tile_linear) gave 25 140 Mcell-steps/s against 24 995 with 128-byte z
+// tiles and 24 600 with 64-byte y tiles (Z1 now runs 128-byte tiles, see the
+// plans below); the pitch stays 128 bytes (a 64-byte pitch makes half of
 // the 128-byte rows straddle two cache lines, a 256-byte pitch slows the y and
 // z passes), and 256-byte z tiles are slower (fewer workgroups per CU).
 #ifndef FWI_Y_TILE_BYTES
 #define FWI_Y_TILE_BYTES 128
 #endif
 #ifndef FWI_ZM_TILE_BYTES
-#define FWI_ZM_TILE_BYTES 64
+#define FWI_ZM_TILE_BYTES 128
 #endif
 #ifndef FWI_ZP_TILE_BYTES
 #define FWI_ZP_TILE_BYTES 64
@@ -84,7 +85,11 @@ namespace fwi {
 //                      25 190 with plan 0: Z2 itself is 3 % slower, but its
 //                      stores leave the caches in a state the following inverse
 //                      y passes and X1 read 2-3 % faster; the other kinds'
-//                      plans change the total by less than 0.1 %.
+//                      plans change the total by less than 0.1 %.  Since v_z
+//                      moved into Z2 (bricked) and Y2 pairs its fields, the
+//                      autotuner picks 128-byte Z1 tiles and Z2 plan 0 (Z1
+//                      0.452 -> 0.424 ms, Y2 0.338 -> 0.325 ms, step -2.6 %;
+//                      Z2's plan no longer matters), the defaults now.
 #ifndef FWI_Y_PLAN
 #define FWI_Y_PLAN 0
 #endif
@@ -92,7 +97,7 @@ namespace fwi {
 #define FWI_ZM_PLAN 0
 #endif
 #ifndef FWI_ZP_PLAN
-#define FWI_ZP_PLAN 1
+#define FWI_ZP_PLAN 0
 #endif
 #ifndef FWI_X_PLAN
 #define FWI_X_PLAN 0
