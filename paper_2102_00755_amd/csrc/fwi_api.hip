@@ -572,10 +572,15 @@ template <typename T> struct Engine : EngineBase {
     return a;
   }
   // tiles per spectrum row of an axis pass of kind k (AxisKind)
-  int ntx(int k) const {
-    const int tw = tile_bytes[k] / (int)sizeof(C);
+  int ntx(int k) const { return ntx_bytes(tile_bytes[k]); }
+  int ntx_bytes(int tb) const {
+    const int tw = tb / (int)sizeof(C);
     return (d.px + tw - 1) / tw;
   }
+  // z passes of the absorption (the lossy Z1 with A[d], the fractional
+  // Laplacian pass): 64-byte tiles whatever the Z1 tuning (at 448x448x224
+  // FP32 the lossy gradient takes 14.4 s with them, 15.8 s with 128-byte ones)
+  static constexpr int kLossyZTile = 64;
 
   // algorithmic bytes of one half spectrum / one real field
   double sbytes() const { return (double)(d.M + 1) * d.ny * d.nz * sizeof(C); }
@@ -635,7 +640,8 @@ template <typename T> struct Engine : EngineBase {
     a1.vz_state = 1;
     if (lossy) {   // with A[d] of the absorption operator: one workgroup per tile and slot
       a1.ad = ad_ptr;
-      FWI_HIP(launch_axis_zma<T>(d.nz, tzm, plans[AK_ZMINUS], dim3(ntx(AK_ZMINUS) * d.ny, nslots), st, a1));  // Z1 + A[d]
+      FWI_HIP(launch_axis_zma<T>(d.nz, kLossyZTile, plans[AK_ZMINUS], dim3(ntx_bytes(kLossyZTile) * d.ny, nslots), st,
+                                 a1));  // Z1 + A[d]
     } else {
       FWI_HIP(launch_axis_zm<T>(d.nz, tzm, plans[AK_ZMINUS], gz3, st, a1));  // Z1
     }
@@ -706,11 +712,11 @@ template <typename T> struct Engine : EngineBase {
     const int s0 = (k0 == SP_ADJOINT) ? 0 : p.batch;
     const int s1 = (k1 < 0) ? s0 : ((k1 == SP_ADJOINT) ? 0 : p.batch);
     const int ns = (k1 < 0) ? B : 2 * B;
-    const int ty = tile_bytes[AK_Y], tz = tile_bytes[AK_ZMINUS];
+    const int ty = tile_bytes[AK_Y], tz = kLossyZTile;
     // B[s] only: A[d] came with the step's Z1
     const AxisArgs<T> ax = axis_args(s0, B, s1, 1, 0);
     FWI_HIP(launch_axis_y<T>(d.ny, false, ty, plans[AK_Y], dim3(ntx(AK_Y) * d.nz, ns), st, ax));
-    FWI_HIP(launch_axis_zf<T>(d.nz, tz, plans[AK_ZMINUS], dim3(ntx(AK_ZMINUS) * d.ny, ns), st, ax));
+    FWI_HIP(launch_axis_zf<T>(d.nz, tz, plans[AK_ZMINUS], dim3(ntx_bytes(tz) * d.ny, ns), st, ax));
     FWI_HIP(launch_axis_y<T>(d.ny, true, ty, plans[AK_Y], dim3(ntx(AK_Y) * d.nz, ns), st, ax));
     const int lpe = x_lines_per_block_eos<T>(d.M);
     const dim3 ge((d.nlines + lpe - 1) / lpe, B);
@@ -1100,12 +1106,12 @@ template <typename T> struct Engine : EngineBase {
     xa.d = d; xa.tb = tb; xa.dt_rho = (T)0;
     const int lpb = x_lines_per_block<T>(d.M);
     const dim3 gx((d.nlines + lpb - 1) / lpb, 1);
-    const int ty = tile_bytes[AK_Y], tz = tile_bytes[AK_ZMINUS];
+    const int ty = tile_bytes[AK_Y], tz = kLossyZTile;
     const AxisArgs<T> ax = axis_args(s, 1, s, 2, 0);
     FWI_HIP(launch_x_r2c<T>(d.M, gx, st, xa, inB, 0));
     FWI_HIP(launch_x_r2c<T>(d.M, gx, st, xa, inA, 1));
     FWI_HIP(launch_axis_y<T>(d.ny, false, ty, plans[AK_Y], dim3(ntx(AK_Y) * d.nz, 2), st, ax));
-    FWI_HIP(launch_axis_zf<T>(d.nz, tz, plans[AK_ZMINUS], dim3(ntx(AK_ZMINUS) * d.ny, 2), st, ax));
+    FWI_HIP(launch_axis_zf<T>(d.nz, tz, plans[AK_ZMINUS], dim3(ntx_bytes(tz) * d.ny, 2), st, ax));
     FWI_HIP(launch_axis_y<T>(d.ny, true, ty, plans[AK_Y], dim3(ntx(AK_Y) * d.nz, 2), st, ax));
     FWI_HIP(launch_x_c2r<T>(d.M, gx, st, xa, outB, 0, nullptr));
     FWI_HIP(launch_x_c2r<T>(d.M, gx, st, xa, outA, 1, nullptr));
