@@ -1271,22 +1271,34 @@ __device__ __forceinline__ int local_line(const int32_t* off, int l0, int nl, in
 // LOSSY: instead of p, column pcol receives s = sum_a rho_a, which is also
 // stored as a real field in the slot's third spectrum buffer (rows of px
 // complex), for the lossy equation of state (A[d] comes from the z pass).
-template <typename T, int M, int LPB, int TWP, int TWPP, int KIND, bool STAGE_TW, bool LOSSY = false, int PL = 0>
-__device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx& si, const Slot<T>& sl, int b,
-                                               int l0, int nl, int state_mode, int pcol, cplx<T>* buf,
-                                               cplx<T>* bufp, cplx<T>* spv, uint8_t* spm, cplx<T>* twl) {
+// The update runs in phases around the C2R so that the paired pass can
+// transform the derivative spectra of both of its simulations at once:
+// density_load (registers: c0, densities, PML factors; the three spectra into
+// LDS columns col0 + f LPB; the sparse inputs into spv / spm), one C2R of all
+// TWP columns (density_c2r), density_finish (the update; p or s to column
+// pcol of bufp).  density_update runs the three for one slot.
+template <typename T, int M, int LPB> struct DensRegs {
+  static constexpr int EB = Lanes<LPB, M>::NI;
+  cplx<T> cc[EB], rr[EB][3], l0f[EB];
+  T l1f[EB], l2f[EB];
+};
+template <typename T, int M, int LPB, int TWP, int KIND, bool STAGE_TW, bool LOSSY>
+__device__ __forceinline__ void density_load(const X2Args<T>& a, const StepIdx& si, const Slot<T>& sl, int b, int l0,
+                                             int nl, int state_mode, int col0, cplx<T>* buf, cplx<T>* spv,
+                                             uint8_t* spm, cplx<T>* twl, DensRegs<T, M, LPB>& r) {
   const bool zero_state = state_mode == 1;
   const bool no_step = state_mode != 0;
   using C = cplx<T>;
-  constexpr int NC = 3 * LPB;
   const int nx = a.d.nx;
   const size_t px = a.d.px;
   const T* cb = a.c + (size_t)b * a.d.nfield;
   // prefetch c0, the split densities and the PML factors: in flight during
   // the C2R transforms
-  constexpr int EB = Lanes<LPB, M>::NI;
-  C cc[EB], rr[EB][3], l0f[EB];
-  T l1f[EB], l2f[EB];
+  C* const cc = r.cc;
+  C(*const rr)[3] = r.rr;
+  C* const l0f = r.l0f;
+  T* const l1f = r.l1f;
+  T* const l2f = r.l2f;
   lanes2d_all<LPB, M>([&](int i, int l, int n, bool) {
     const int line = l0 + min(l, nl - 1);
     const size_t lo = (size_t)line * nx;
@@ -1316,7 +1328,7 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx
       });
     }
     if (STAGE_TW) x_tw_prefetch<T, M>(tt, a.tb);
-    if (!no_step) x_commit_spectra<T, M, LPB, TWP, 3>(buf, pre, 0);
+    if (!no_step) x_commit_spectra<T, M, LPB, TWP, 3>(buf, pre, col0);
     if (STAGE_TW) x_tw_commit<T, M>(twl, tt);
   }
   for (int e = threadIdx.x; e < M * LPB; e += X_NT) {
@@ -1361,13 +1373,29 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx
       spm[q] = 1;
     }
   }
-  if (!no_step) {
-    c2r_pre<T, M, TWP, NC>(buf, twl + M);
-    __syncthreads();
-    lds_fft<T, M, NC, TWP, X_NT, true, PL>(buf, twl);
-  } else {
-    __syncthreads();
-  }
+}
+// inverse x transforms of all TWP columns of buf (after density_load)
+template <typename T, int M, int TWP, int PL>
+__device__ __forceinline__ void density_c2r(cplx<T>* buf, const cplx<T>* twl) {
+  c2r_pre<T, M, TWP, TWP>(buf, twl + M);
+  __syncthreads();
+  lds_fft<T, M, TWP, TWP, X_NT, true, PL>(buf, twl);
+}
+template <typename T, int M, int LPB, int TWP, int TWPP, int KIND, bool LOSSY>
+__device__ __forceinline__ void density_finish(const X2Args<T>& a, const Slot<T>& sl, int l0, int nl,
+                                               int state_mode, int col0, int pcol, const cplx<T>* buf,
+                                               cplx<T>* bufp, const cplx<T>* spv, const uint8_t* spm,
+                                               const DensRegs<T, M, LPB>& r) {
+  const bool zero_state = state_mode == 1;
+  const bool no_step = state_mode != 0;
+  using C = cplx<T>;
+  const int nx = a.d.nx;
+  const size_t px = a.d.px;
+  const C* const cc = r.cc;
+  const C(*const rr)[3] = r.rr;
+  const C* const l0f = r.l0f;
+  const T* const l1f = r.l1f;
+  const T* const l2f = r.l2f;
   lanes2d<LPB, M>([&](int i, int l, int n) {
     if (l >= nl) return;
     const int line = l0 + l;
@@ -1385,7 +1413,8 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx
         u = rr[i][0];
         rx = rr[i][1];
       } else {
-        const C d0 = buf[n * TWP + l], d1 = buf[n * TWP + LPB + l], d2 = buf[n * TWP + 2 * LPB + l];
+        const C d0 = buf[n * TWP + col0 + l], d1 = buf[n * TWP + col0 + LPB + l],
+                d2 = buf[n * TWP + col0 + 2 * LPB + l];
         const C du = xp ? cadd(d1, d2) : cadd(cadd(d0, d1), d2);
         u = cmake<C>(rr[i][0].x - a.dt_rho0 * du.x, rr[i][0].y - a.dt_rho0 * du.y);
         if (xp) {
@@ -1414,7 +1443,7 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx
       } else if (no_step) {
         rn = rr[i][f];
       } else {
-        const C dv = buf[n * TWP + f * LPB + l];
+        const C dv = buf[n * TWP + col0 + f * LPB + l];
         const T lx = f == 0 ? l0f[i].x : (f == 1 ? l1f[i] : l2f[i]);
         const T ly = f == 0 ? l0f[i].y : (f == 1 ? l1f[i] : l2f[i]);
         rn = cmake<C>(lx * (lx * rr[i][f].x - a.dt_rho0 * dv.x), ly * (ly * rr[i][f].y - a.dt_rho0 * dv.y));
@@ -1437,6 +1466,17 @@ __device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx
   });
   __syncthreads();
 }
+template <typename T, int M, int LPB, int TWP, int TWPP, int KIND, bool STAGE_TW, bool LOSSY = false, int PL = 0>
+__device__ __forceinline__ void density_update(const X2Args<T>& a, const StepIdx& si, const Slot<T>& sl, int b,
+                                               int l0, int nl, int state_mode, int pcol, cplx<T>* buf,
+                                               cplx<T>* bufp, cplx<T>* spv, uint8_t* spm, cplx<T>* twl) {
+  static_assert(TWP == 3 * LPB, "one slot: three spectra of LPB lines");
+  DensRegs<T, M, LPB> r;
+  density_load<T, M, LPB, TWP, KIND, STAGE_TW, LOSSY>(a, si, sl, b, l0, nl, state_mode, 0, buf, spv, spm, twl, r);
+  if (state_mode == 0) density_c2r<T, M, TWP, PL>(buf, twl);
+  else __syncthreads();
+  density_finish<T, M, LPB, TWP, TWPP, KIND, LOSSY>(a, sl, l0, nl, state_mode, 0, pcol, buf, bufp, spv, spm, r);
+}
 
 // read p at voxel x of local line l from the packed column pcol
 template <typename T, int TWPP>
@@ -1457,11 +1497,11 @@ __global__ void __launch_bounds__(X_NT) k_x_density(X2Args<T> a) {
   using C = cplx<T>;
   constexpr int LPB = x_lpb_den_mode<T>(M, MODE);
   constexpr int NP = (MODE == XM_PAIR) ? 2 : 1;
-  constexpr int TWP = 3 * LPB;        // d-_a v_a of the three axes
+  constexpr int TWP = 3 * LPB * NP;   // d-_a v_a of the three axes (per simulation)
   constexpr int TWPP = NP * LPB;      // new pressure(s), packed for the R2C
   __shared__ C buf[(M + 1) * TWP];
   __shared__ C bufp[(M + 1) * TWPP];
-  __shared__ C spv[M * LPB];
+  __shared__ C spv[M * LPB * NP];
   __shared__ uint8_t spm[(MODE == XM_PAIR || MODE == XM_TRONLY) ? 2 * M * LPB : 1];
   __shared__ C twl[XTw<M>::N];
   const int l0 = blockIdx.x * LPB;
@@ -1475,7 +1515,7 @@ __global__ void __launch_bounds__(X_NT) k_x_density(X2Args<T> a) {
   const Slot<T> s_tr = a.slots[a.tr_off + b];
   const StepIdx si = step_indices<T, MODE>(a);
 
-  if (MODE == XM_FWD) {
+  if constexpr (MODE == XM_FWD) {
     density_update<T, M, LPB, TWP, TWPP, SP_SOURCE, true, false, PL>(a, si, s_tr, b, l0, nl, 0, PA, buf, bufp, spv, spm,
                                                           twl);
     // sensors f^n = M p and boundary tape g^n = p(dGamma)
@@ -1504,11 +1544,23 @@ __global__ void __launch_bounds__(X_NT) k_x_density(X2Args<T> a) {
       }
     }
   }
-  if (MODE == XM_PAIR || MODE == XM_ADJONLY) {
+  if constexpr (MODE == XM_PAIR) {
+    // adjoint (columns 0 ..) and TR (columns 3 LPB ..) through one C2R
+    DensRegs<T, M, LPB> ra, rt;
+    C* const spv_t = spv + M * LPB;
+    density_load<T, M, LPB, TWP, SP_ADJOINT, true, false>(a, si, s_adj, b, l0, nl, 0, 0, buf, spv, nullptr, twl, ra);
+    density_load<T, M, LPB, TWP, SP_DIRICHLET, false, false>(a, si, s_tr, b, l0, nl, a.tr_state_mode, 3 * LPB, buf,
+                                                             spv_t, spm, twl, rt);
+    density_c2r<T, M, TWP, PL>(buf, twl);
+    density_finish<T, M, LPB, TWP, TWPP, SP_ADJOINT, false>(a, s_adj, l0, nl, 0, 0, PA, buf, bufp, spv, nullptr, ra);
+    density_finish<T, M, LPB, TWP, TWPP, SP_DIRICHLET, false>(a, s_tr, l0, nl, a.tr_state_mode, 3 * LPB, PT, buf, bufp,
+                                                              spv_t, spm, rt);
+  }
+  if constexpr (MODE == XM_ADJONLY) {
     density_update<T, M, LPB, TWP, TWPP, SP_ADJOINT, true, false, PL>(a, si, s_adj, b, l0, nl, 0, PA, buf, bufp, spv,
                                                            spm, twl);
   }
-  if (MODE == XM_PAIR || MODE == XM_TRONLY) {
+  if constexpr (MODE == XM_TRONLY) {
     density_update<T, M, LPB, TWP, TWPP, SP_DIRICHLET, MODE == XM_TRONLY, false, PL>(a, si, s_tr, b, l0, nl, a.tr_state_mode,
                                                                           PT, buf, bufp, spv, spm, twl);
   }
